@@ -1,0 +1,109 @@
+"""Graph Laplacian in FP64 (oracle; test infrastructure only).
+
+Paper: Sec. 3.2 (Spectral Graph Partitioning).  The combinatorial Laplacian is
+L_C = D - A (Eq. 2); for weighted graphs the off-diagonal entries are the
+negated edge weights and the diagonal holds the sum of incident weights (the
+paragraph after Eq. 3).  The generalized problem is L_C x = lambda D x.
+
+Reading taken (self-loops): the paper symmetrises inputs as A + A^T + I
+(Sec. 6.1) but Eq. 2 only uses off-diagonal adjacency, so self-loops carry no
+weight here; inputs have none.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+COMBINATORIAL = 0
+GENERALIZED = 1
+
+
+def _weights(col, w):
+    return np.ones(col.shape[0], dtype=np.float64) if w is None else np.asarray(w, dtype=np.float64)
+
+
+def row_index(rowptr):
+    """Row id of every CSR entry."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    return np.repeat(np.arange(rowptr.size - 1, dtype=np.int64), np.diff(rowptr))
+
+
+def degrees(rowptr, col, w=None):
+    """Weighted degree d_i = sum_j w_ij (the diagonal of L_C, Eq. 2 weighted)."""
+    ww = _weights(col, w)
+    r = row_index(rowptr)
+    return np.bincount(r, weights=ww, minlength=len(rowptr) - 1).astype(np.float64)
+
+
+def pattern_degrees(rowptr):
+    """Number of neighbours of each vertex (the paper's "degree")."""
+    return np.diff(np.asarray(rowptr, dtype=np.int64))
+
+
+def is_regular(rowptr):
+    """Sec. 6.1: a graph is regular iff max degree / average degree <= 10."""
+    deg = pattern_degrees(rowptr)
+    n = deg.size
+    if n == 0 or deg.sum() == 0:
+        return True
+    return deg.max() * n <= 10 * deg.sum()
+
+
+def apply(rowptr, col, w, X):
+    """Y = L_C X in FP64, written as (L x)_i = sum_j w_ij (x_i - x_j).
+
+    This is (D - A) x of Eq. 2 with weights, summed in difference form so that
+    a constant vector maps to exactly zero.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    squeeze = X.ndim == 1
+    if squeeze:
+        X = X[:, None]
+    ww = _weights(col, w)
+    r = row_index(rowptr)
+    contrib = ww[:, None] * (X[r] - X[np.asarray(col, dtype=np.int64)])
+    Y = np.zeros_like(X)
+    np.add.at(Y, r, contrib)
+    return Y[:, 0] if squeeze else Y
+
+
+def dense(rowptr, col, w, n=None):
+    """Dense (L_C, d) built entry by entry from Eq. 2: L_ii = d_i, L_ij = -w_ij."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    n = rowptr.size - 1 if n is None else n
+    ww = _weights(col, w)
+    L = np.zeros((n, n), dtype=np.float64)
+    for i in range(n):
+        for k in range(rowptr[i], rowptr[i + 1]):
+            j = int(col[k])
+            L[i, j] -= ww[k]
+            L[i, i] += ww[k]
+    return L, np.diag(L).copy()
+
+
+def bdiag(rowptr, col, w, problem):
+    """Diagonal of B: ones (combinatorial, L x = lambda x) or the weighted degrees
+    (generalized, L x = lambda D x), Sec. 3.2."""
+    n = len(rowptr) - 1
+    if problem == COMBINATORIAL:
+        return np.ones(n, dtype=np.float64)
+    return degrees(rowptr, col, w)
+
+
+def residual_norms(LX, X, theta, bd):
+    """Relative residuals rho_i of Ritz pairs (theta_i, x_i).
+
+    Reading taken (the paper gives tolerance values, Sec. 6.3.2, but no norm):
+      rho_i = ||L x_i - theta_i B x_i||_{B^-1} / (max(theta_i, theta_1) ||x_i||_B)
+    i.e. the relative residual of the equivalent standard problem
+    B^-1/2 L B^-1/2, with theta_1 (the smallest non-trivial Ritz value) as a
+    floor so that the trivial pair theta_0 ~ 0 is measured on the same scale.
+    theta must be sorted ascending.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    R = LX - (bd[:, None] * X) * theta[None, :]
+    rn = np.sqrt(np.sum(R * R / bd[:, None], axis=0))
+    xn = np.sqrt(np.sum(bd[:, None] * X * X, axis=0))
+    floor = theta[1] if theta.size > 1 else theta[0]
+    scale = np.maximum(theta, floor)
+    scale = np.where(scale > 0, scale, 1.0)
+    return rn / (scale * xn)

@@ -1,0 +1,179 @@
+"""Pins for oracle.precond, oracle.split and oracle.quality (CPU only)."""
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+from oracle import laplacian as lap, precond, quality, split
+from tests import closed_forms as cf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- precond
+
+def test_jacobi_hand_example():
+    R = np.array([[2.0, -4.0], [3.0, 9.0]])
+    assert np.array_equal(precond.jacobi(R, np.array([2.0, 3.0])), [[1.0, -2.0], [1.0, 3.0]])
+
+
+@pytest.mark.parametrize("degree,ratio", [(1, 4.0), (5, 10.0), (25, 30.0)])
+def test_chebyshev_on_eigenvectors_matches_closed_form(degree, ratio):
+    n = 40
+    u = np.arange(n - 1)
+    g = graphgen.csr_from_edges(n, u, u + 1)
+    d = lap.degrees(g.rowptr, g.col, None)
+    hi = precond.gershgorin_bound(d, lap.COMBINATORIAL)
+    assert hi == 4.0
+    ks = [1, 7, 20, 39]
+    V = np.stack([cf.path_eigvec(n, k) for k in ks], axis=1)
+    H = precond.chebyshev(g.rowptr, g.col, None, V, degree, hi / ratio, hi)
+    for col, k in enumerate(ks):
+        mu = cf.path_eigval(n, k)
+        p = precond.chebyshev_scalar(mu, degree, hi / ratio, hi)
+        assert p > 0
+        assert np.allclose(H[:, col], p * V[:, col], rtol=1e-10, atol=1e-12)
+
+
+def test_chebyshev_generalized_on_torus():
+    n, u, v = cf.torus_edges(5, 4)
+    g = graphgen.csr_from_edges(n, u, v)
+    d = lap.degrees(g.rowptr, g.col, None)
+    # torus eigenvector cos(2 pi a x / nx); D^-1 L has eigenvalue lam/4
+    x = np.cos(2 * np.pi * 2 * (np.arange(n) % 5) / 5)
+    lam = 2 - 2 * np.cos(2 * np.pi * 2 / 5)
+    H = precond.chebyshev(g.rowptr, g.col, None, x[:, None], 6, 0.1, 2.0, dinv=1.0 / d)
+    # h = p(D^-1 L) D^-1 r = p(lam/4) x / 4
+    p = precond.chebyshev_scalar(lam / 4, 6, 0.1, 2.0)
+    assert np.allclose(H[:, 0], p * x / 4, atol=1e-12)
+
+
+def test_chebyshev_polynomial_positive_on_spectrum():
+    xs = np.linspace(1e-6, 12.0, 2001)
+    assert np.all(precond.chebyshev_scalar(xs, 25, 12.0 / 30, 12.0) > 0)
+
+
+# ---------------------------------------------------------------- split
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append(line.split())
+    return rows
+
+
+def test_split_golden_hand_example():
+    rows = _read_golden("split_k4_hand.txt")
+    coords = np.array([[float(r[0]), float(r[1])] for r in rows])
+    expect = np.array([int(r[2]) for r in rows])
+    assert np.array_equal(split.split_pow2(coords, 4), expect)
+
+
+def test_split_weighted_hand_example():
+    # one coordinate, weights 3,1,1,1 (sorted order by value): W = 6;
+    # prefixes W_lo = 0,3,4,5,6 -> |2W_lo - 6| = 6,0,2,4,6 -> prefix of 1
+    coords = np.array([0.4, 0.1, 0.3, 0.2])
+    vw = np.array([1, 3, 1, 1])
+    assert list(split.split_pow2(coords, 2, vw)) == [1, 0, 1, 1]
+    # weights 1,2,2,1 sorted: W = 6: W_lo = 0,1,3,5,6 -> 6,4,0,4,6 -> prefix 2
+    vw = np.array([1, 1, 2, 2])       # sorted by value: ids 1,3,2,0 weights 1,2,2,1
+    assert list(split.split_pow2(coords, 2, vw)) == [1, 0, 1, 0]
+
+
+@pytest.mark.parametrize("n,K", [(1000, 64), (37, 8), (5, 4), (4, 4), (130, 2)])
+def test_split_sizes_and_order(n, K):
+    rng = np.random.default_rng(n)
+    coords = rng.standard_normal((n, 6))
+    part = split.split_pow2(coords, K)
+    sizes = np.bincount(part, minlength=K)
+    assert sizes.min() >= n // K and sizes.max() <= -(-n // K)
+    # first level: everything in the lower half precedes the upper half on coord 0
+    lo = coords[(part >> (K.bit_length() - 2)) == 0, 0] if K > 1 else None
+    hi = coords[(part >> (K.bit_length() - 2)) == 1, 0] if K > 1 else None
+    assert lo.max() <= hi.min()
+
+
+def test_split_ties_broken_by_vertex_id_and_signed_zero():
+    coords = np.zeros((10, 1))
+    coords[::2, 0] = -0.0
+    part = split.split_pow2(coords, 2)
+    assert list(part) == [0] * 5 + [1] * 5
+
+
+def test_split_matches_bruteforce_recursive_sort():
+    rng = np.random.default_rng(9)
+    n, K = 23, 8
+    coords = np.round(rng.standard_normal((n, 3)), 1)     # many exact ties
+    def brute(ids, level):
+        if level == 3:
+            return {i: 0 for i in ids}
+        order = sorted(ids, key=lambda i: (coords[i, level], i))
+        low, high = order[: len(order) // 2], order[len(order) // 2:]
+        out = {}
+        for i, p in brute(low, level + 1).items():
+            out[i] = p
+        for i, p in brute(high, level + 1).items():
+            out[i] = p + (1 << (2 - level))
+        return out
+    b = brute(list(range(n)), 0)
+    assert list(split.split_pow2(coords, K)) == [b[i] for i in range(n)]
+
+
+# ---------------------------------------------------------------- quality
+
+def test_cut_grid_halves_and_quadrants():
+    g = graphgen.config_graph("grid64")
+    x = np.arange(g.n) % 64
+    y = np.arange(g.n) // 64
+    assert quality.cutsize(g.rowptr, g.col, None, (x >= 32).astype(int)) == (64.0, 128.0)
+    quad = (x >= 32).astype(int) + 2 * (y >= 32).astype(int)
+    assert quality.cutsize(g.rowptr, g.col, None, quad)[0] == 128.0
+    assert quality.imbalance(quad, 4) == 1.0
+
+
+@pytest.mark.slow
+def test_cut_grid128_blocks():
+    g = graphgen.config_graph("grid7_128")
+    i = np.arange(g.n)
+    x, y, z = i % 128, (i // 128) % 128, i // (128 * 128)
+    part = (x // 32) + 4 * (y // 32) + 16 * (z // 32)
+    # 3 cut planes per axis, 128^2 edges each
+    assert quality.cutsize(g.rowptr, g.col, None, part)[0] == 9 * 128 * 128
+
+
+def test_cut_equals_quarter_quadratic_form_and_kway_identity():
+    rng = np.random.default_rng(4)
+    n, p = 60, 0.1
+    iu, ju = np.triu_indices(n, 1)
+    keep = rng.random(iu.size) < p
+    w = graphgen.uniform_weights(int(keep.sum()), 5, dtype=np.float64)
+    g = graphgen.csr_from_edges(n, iu[keep], ju[keep], w)
+    part = rng.integers(0, 2, n)
+    x = 2.0 * part - 1.0
+    q = x @ lap.apply(g.rowptr, g.col, g.w, x) / 4.0      # Sec. 3.2
+    assert quality.cutsize(g.rowptr, g.col, g.w, part)[0] == pytest.approx(q, rel=1e-13)
+    part = rng.integers(0, 5, n)
+    chi = np.stack([(part == k).astype(float) for k in range(5)], axis=1)
+    tot = 0.5 * np.sum(chi * lap.apply(g.rowptr, g.col, g.w, chi))
+    assert quality.cutsize(g.rowptr, g.col, g.w, part)[0] == pytest.approx(tot, rel=1e-13)
+
+
+def test_cut_sum_is_exact():
+    # 2^53 + 1 + 1: naive left-to-right float sum loses both ones
+    g = graphgen.csr_from_edges(4, np.array([0, 1, 2]), np.array([1, 2, 3]),
+                                np.array([2.0 ** 53, 1.0, 1.0]))
+    cut, _ = quality.cutsize(g.rowptr, g.col, g.w, np.array([0, 1, 0, 1]))
+    assert cut == 2.0 ** 53 + 2.0
+
+
+def test_part_weights_and_imbalance():
+    part = np.array([0, 0, 1, 2, 2, 2])
+    assert list(quality.part_weights(part, 3)) == [2, 1, 3]
+    assert quality.imbalance(part, 3) == 1.5
+    assert quality.imbalance(part, 3, vwgt=np.array([1, 1, 4, 1, 1, 0])) == 4 * 3 / 8
+    with pytest.raises(ValueError):
+        quality.part_weights(np.array([0, 3]), 3)

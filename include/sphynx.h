@@ -1,0 +1,260 @@
+/*
+ * sphynx.h -- C ABI of an MI355X (gfx950) spectral graph partitioner.
+ *
+ * Method: Sphynx (Acer, Boman, Glusa, Rajamanickam, arXiv 2105.00578).  Given
+ * a symmetric graph G = (V, E) with edge weights and a part count K, compute
+ * the d = floor(log2 K) + 1 smallest eigenpairs of the graph Laplacian by
+ * preconditioned LOBPCG, embed each vertex at its entries of eigenvectors
+ * 2..d, and split the embedding into K parts (Algorithm 2).
+ *
+ * Conventions shared by every entry point
+ *   - Graphs are CSR: row_ptr[n+1] (int32 or int64), col[nnz] (int32),
+ *     optional edge weights w[nnz] (float32 or float64; NULL = unit), optional
+ *     vertex weights vwgt[n] (positive int32; NULL = unit).  The pattern and
+ *     the weights must be symmetric, with no self-loops and no duplicate
+ *     entries.  Column indices need not be sorted.
+ *   - Dense blocks of vectors are row-major (vertex-major): entry (i, c) of an
+ *     n x m block lives at X[i * m + c].
+ *   - "device" pointers are HIP device memory on the handle's device; "host"
+ *     pointers are ordinary host memory.  All device pointers are borrowed:
+ *     the caller keeps them alive (and unmodified, for graph arrays) for as
+ *     long as the object that uses them.
+ *   - Every call is ordered on the handle's HIP stream.  Calls that return
+ *     host results synchronise that stream before returning.
+ *   - Return value: SPHX_OK (0), SPHX_NOT_CONVERGED (+1, a warning: outputs
+ *     hold the best iterate), or a negative error code.  No C++ exception
+ *     crosses this interface.  sphx_last_error() gives a message.
+ *   - A handle must not be used by two host threads at once.
+ */
+#ifndef SPHYNX_H
+#define SPHYNX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+enum {
+    SPHX_OK = 0,
+    SPHX_NOT_CONVERGED = 1,     /* warning: max_iter reached               */
+    SPHX_E_INVALID_ARG = -1,    /* bad size, pointer, option or K          */
+    SPHX_E_BAD_GRAPH = -2,      /* row_ptr not monotone, col out of range,
+                                   duplicate entries                       */
+    SPHX_E_NOT_SYMMETRIC = -3,  /* pattern or weights not symmetric        */
+    SPHX_E_BAD_WEIGHT = -4,     /* edge weight not finite and > 0, or
+                                   vertex weight < 1                       */
+    SPHX_E_SELF_LOOP = -5,      /* an entry (i, i)                          */
+    SPHX_E_BREAKDOWN = -6,      /* Rayleigh-Ritz basis lost rank even after
+                                   restarting without the P block          */
+    SPHX_E_HIP = -7,            /* a HIP runtime call failed               */
+    SPHX_E_WORKSPACE = -8       /* workspace too small / allocation failed */
+};
+
+/* dtype tags for untyped pointers */
+enum { SPHX_UNIT = 0, SPHX_F32 = 1, SPHX_F64 = 2 };
+
+/* eigenvalue problem (Sec. 3.2): L_C x = lambda x, or L_C x = lambda D x */
+enum { SPHX_COMBINATORIAL = 0, SPHX_GENERALIZED = 1 };
+
+/* preconditioner (Sec. 5): none, Jacobi (Sec. 5.1), Chebyshev polynomial
+ * (Sec. 5.2 names a degree-25 polynomial preconditioner) */
+enum { SPHX_PRECOND_NONE = 0, SPHX_PRECOND_JACOBI = 1, SPHX_PRECOND_CHEBYSHEV = 2 };
+
+/* arithmetic: all FP64, or FP32 sparse products / preconditioner / vector
+ * updates with FP64 Gram matrices, Rayleigh-Ritz and norms */
+enum { SPHX_FP64 = 0, SPHX_MIXED = 1 };
+
+/* initial block (Sec. 6.2.1): random (default on regular graphs),
+ * piecewise constant (default on irregular graphs), or caller supplied */
+enum { SPHX_INIT_RANDOM = 0, SPHX_INIT_PIECEWISE = 1, SPHX_INIT_USER = 2 };
+
+/* graph flags */
+enum { SPHX_SKIP_VALIDATE = 1u };
+
+typedef struct sphx_handle sphx_handle;
+typedef struct sphx_graph sphx_graph;
+
+typedef struct sphx_options {
+    int problem;          /* SPHX_COMBINATORIAL / SPHX_GENERALIZED          */
+    int precond;          /* SPHX_PRECOND_*                                  */
+    int cheb_degree;      /* SpMMs per Chebyshev apply (default 25)          */
+    double cheb_ratio;    /* Chebyshev interval [hi/ratio, hi]; hi is the
+                             Gershgorin bound (2 max_i d_i, or 2 for D^-1 L) */
+    int precision;        /* SPHX_FP64 / SPHX_MIXED                          */
+    double tol;           /* bound on every relative residual rho_i:
+                             ||L x_i - theta_i B x_i||_{B^-1}
+                               / (max(theta_i, theta_1) ||x_i||_B)            */
+    int max_iter;         /* LOBPCG iterations (default 10000)               */
+    int init;             /* SPHX_INIT_*                                      */
+    uint64_t seed;        /* for SPHX_INIT_RANDOM                             */
+    int locking;          /* soft locking (Algorithm 1 "I" subsets), 1/0     */
+    double drop_tol;      /* Rayleigh-Ritz basis directions with relative
+                             Gram eigenvalue below this are dropped; 0 picks
+                             1e-10 (MIXED) or 1e-14 (FP64)                   */
+} sphx_options;
+
+typedef struct sphx_stats {
+    int iterations;       /* LOBPCG iterations done                           */
+    int converged;        /* number of eigenpairs with rho_i <= tol           */
+    int restarts;         /* Rayleigh-Ritz restarts without the P block       */
+    int graph_regular;    /* 1 iff max degree / average degree <= 10          */
+    int64_t max_degree;
+    double avg_degree;
+    double rho[32];       /* final rho_i from one FP64 product L X (first 32) */
+    double ms_total;      /* device time of the call (HIP events)             */
+    double ms_setup, ms_spmm, ms_precond, ms_gram, ms_rr, ms_update,
+           ms_split, ms_quality;   /* per-phase device time, only when the
+                                      handle's timing flag is on             */
+    int64_t spmm_calls;   /* Laplacian products launched (all kinds)         */
+} sphx_stats;
+
+/* ---------------------------------------------------------------- basics */
+
+/* Message for a status code (static string). */
+const char *sphx_status_string(int status);
+
+/* Create a handle on HIP device `device`, ordering work on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  *h receives the handle. */
+int sphx_create(sphx_handle **h, int device, void *hip_stream);
+int sphx_destroy(sphx_handle *h);
+int sphx_set_stream(sphx_handle *h, void *hip_stream);
+/* Last error message of this handle ("" if none). */
+const char *sphx_last_error(const sphx_handle *h);
+/* Per-phase timing with HIP events (adds synchronisation; off by default). */
+int sphx_set_timing(sphx_handle *h, int on);
+
+/* Eq. 4: number of eigenvectors d = floor(log2 K) + 1 (K >= 1), else -1. */
+int sphx_num_eigenvectors(int K);
+
+/* Defaults of Sec. 6.3.1 ("Sphynx Default Settings") for a preconditioner:
+ * regular graphs use the combinatorial problem, irregular graphs the
+ * generalized one; the tolerance is 1e-3 on regular graphs and 1e-2 on
+ * irregular ones; initial vectors are random on regular graphs and piecewise
+ * constant on irregular ones (Sec. 6.2.1).  (The paper's normalized-Laplacian
+ * choice for irregular graphs with a polynomial preconditioner is not
+ * offered; the generalized problem is used instead.) */
+void sphx_options_default(sphx_options *opt, int graph_is_regular, int precond);
+
+/* ---------------------------------------------------------------- graphs */
+
+/* Wrap a device CSR graph (Sec. 3.1).  row_ptr: device int32[n+1]
+ * (row_ptr_is_64 = 0) or int64[n+1] (= 1).  col: device int32[nnz].
+ * w: device edge weights of type w_dtype (SPHX_F32/SPHX_F64) or NULL with
+ * SPHX_UNIT.  vwgt: device int32[n] vertex weights (>= 1) or NULL (unit).
+ * Unless flags has SPHX_SKIP_VALIDATE, the arrays are checked on the device
+ * (monotone row_ptr, 0 <= col < n, no self-loops, no duplicates, symmetric
+ * pattern and weights, weights finite and > 0): errors SPHX_E_BAD_GRAPH,
+ * SPHX_E_SELF_LOOP, SPHX_E_NOT_SYMMETRIC, SPHX_E_BAD_WEIGHT.  Connectivity is
+ * not checked: with c components, eigenvalue 0 has multiplicity c.
+ * Requires 1 <= n < 2^31 and nnz < 2^31 (int32 row_ptr) or < 2^62. */
+int sphx_graph_create(sphx_handle *h, int64_t n, int64_t nnz,
+                      const void *row_ptr, int row_ptr_is_64,
+                      const int32_t *col, const void *w, int w_dtype,
+                      const int32_t *vwgt, uint32_t flags, sphx_graph **g);
+int sphx_graph_destroy(sphx_graph *g);
+
+/* Degree statistics of Sec. 6.1: regular iff max/avg degree <= 10.
+ * Pattern degrees (neighbour counts). Synchronises. */
+int sphx_graph_info(sphx_handle *h, sphx_graph *g, int *is_regular,
+                    int64_t *max_degree, double *avg_degree);
+
+/* --------------------------------------------------------------- workspace */
+
+/* Device bytes needed by sphx_eigensolve / sphx_partition / sphx_eig_backward
+ * for this graph, nev and options (an upper bound for all of them). */
+int sphx_workspace_size(sphx_handle *h, sphx_graph *g, int nev,
+                        const sphx_options *opt, size_t *bytes);
+/* Hand the library a device workspace (borrowed).  Calls that need more than
+ * `bytes` allocate (and cache) their own instead.  NULL detaches it. */
+int sphx_set_workspace(sphx_handle *h, void *dev_ptr, size_t bytes);
+
+/* -------------------------------------------------------------- operators */
+
+/* Y = L_C X (Eq. 2 with weights), X and Y device n x m blocks of dtype
+ * SPHX_F32 or SPHX_F64 (1 <= m <= 32).  Summed per row as
+ * sum_j w_ij (x_i - x_j), so constant vectors map to exact zeros. */
+int sphx_laplacian_apply(sphx_handle *h, sphx_graph *g, int m, int dtype,
+                         const void *X, void *Y);
+
+/* H = T R for the LOBPCG preconditioner T of `opt` (Sec. 5; Algorithm 1
+ * "solve M H = R"): Jacobi h_ic = r_ic / d_i; Chebyshev: cheb_degree steps of
+ * the Chebyshev iteration for L h = r (generalized: D^-1 L h = D^-1 r) from
+ * h = 0 on [hi/cheb_ratio, hi]; NONE copies.  R, H: device n x m, dtype. */
+int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *opt,
+                       int m, int dtype, const void *R, void *H);
+
+/* -------------------------------------------------------------- eigensolve */
+
+/* The nev smallest eigenpairs of L_C x = lambda B x (B = I or D), by LOBPCG
+ * (Algorithm 1) with block size nev (Sec. 4).
+ * X0: device n x nev initial block (dtype of the precision: F32 for MIXED,
+ *     F64 for FP64), read only when opt->init == SPHX_INIT_USER, else NULL.
+ * eigvals: host double[nev], ascending.
+ * eigvecs: device n x nev (F32 for MIXED, F64 for FP64), B-orthonormal, each
+ *     column's largest-magnitude entry (lowest index on ties) positive.
+ * stats: host, may be NULL.  1 <= nev <= 32, nev < n.
+ * Returns SPHX_NOT_CONVERGED if max_iter was reached first. */
+int sphx_eigensolve(sphx_handle *h, sphx_graph *g, int nev,
+                    const sphx_options *opt, const void *X0,
+                    double *eigvals, void *eigvecs, sphx_stats *stats);
+
+/* ------------------------------------------------------------ split, cut */
+
+/* Part vector from coordinates (Algorithm 2, MJ special case for K = 2^m):
+ * level l bisects every section along coordinate l mod ncoord; members are
+ * ordered by (value, vertex id) with -0 == +0; the lower child gets the
+ * prefix whose weight W_lo minimises |2 W_lo - W|, the shorter on ties; part
+ * ids are branch bits, most significant first.
+ * coords: device, entry (i, c) at coords[i * ld + c], dtype F32 or F64,
+ * 1 <= ncoord <= ld.  part: device int32[n].  K must be a power of two,
+ * 1 <= K <= 2^30.  NaN coordinates give SPHX_E_INVALID_ARG. */
+int sphx_split(sphx_handle *h, sphx_graph *g, const void *coords, int ld,
+               int ncoord, int dtype, int K, int32_t *part);
+
+/* Partition quality (Sec. 3.1): cut = Eq. 1 (each undirected edge once),
+ * cut2x = 2 cut (the paper's table convention), part weights W_k and
+ * imbalance = max_k W_k * K / sum_k W_k.  Sums are exact before a single
+ * final rounding (weights must span at most 2^40 in ratio).
+ * part: device int32[n] with values in [0, K).  cut, cut2x, imbalance: host
+ * (each may be NULL).  part_weights: host int64[K] or NULL. */
+int sphx_quality(sphx_handle *h, sphx_graph *g, const int32_t *part, int K,
+                 double *cut, double *cut2x, double *imbalance,
+                 int64_t *part_weights);
+
+/* Algorithm 2 end to end: nev = d = floor(log2 K) + 1 eigenpairs, the
+ * embedding = eigenvector columns 1..d-1 (the trivial one dropped), the
+ * split and its quality.  eigvals host double[d]; eigvecs device n x d (as
+ * in sphx_eigensolve; may be NULL to use workspace); part device int32[n];
+ * cut, imbalance host (may be NULL). */
+int sphx_partition(sphx_handle *h, sphx_graph *g, int K, const sphx_options *opt,
+                   const void *X0, double *eigvals, void *eigvecs,
+                   int32_t *part, double *cut, double *imbalance,
+                   sphx_stats *stats);
+
+/* ---------------------------------------------------------------- adjoint */
+
+/* Gradient of a loss l(lambda, V) with respect to the edge weights, through
+ * the eigenpairs of L_C x = lambda B x (weighted Laplacian, Sec. 3.2).
+ * Inputs: eigvals host double[nev] (simple eigenvalues), eigvecs device F64
+ * n x nev (B-orthonormal eigenvectors, e.g. from sphx_eigensolve in FP64),
+ * g_vals host double[nev] (dl/dlambda, NULL = 0), g_vecs device F64 n x nev
+ * (dl/dV, NULL = 0).  Output grad_w: device F64[nnz]; both stored directions
+ * of an undirected edge receive dl/dw_e for that edge.
+ * Eigenvector terms inside the block use the computed pairs; the rest of the
+ * spectrum enters through mu_k solving (L - lambda_k B) mu_k =
+ * g_k - B V V^T g_k with V^T B mu_k = 0 (projected, Jacobi-preconditioned
+ * conjugate gradients to relative residual cg_tol, at most cg_max_iter).
+ * The graph must carry F64 weights or unit weights.
+ * Returns SPHX_NOT_CONVERGED if a CG solve stopped at cg_max_iter. */
+int sphx_eig_backward(sphx_handle *h, sphx_graph *g, int problem, int nev,
+                      const double *eigvals, const void *eigvecs,
+                      const double *g_vals, const void *g_vecs,
+                      double cg_tol, int cg_max_iter, void *grad_w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPHYNX_H */

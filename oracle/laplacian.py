@@ -11,6 +11,8 @@ weight here; inputs have none.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 COMBINATORIAL = 0
@@ -28,10 +30,14 @@ def row_index(rowptr):
 
 
 def degrees(rowptr, col, w=None):
-    """Weighted degree d_i = sum_j w_ij (the diagonal of L_C, Eq. 2 weighted)."""
-    ww = _weights(col, w)
-    r = row_index(rowptr)
-    return np.bincount(r, weights=ww, minlength=len(rowptr) - 1).astype(np.float64)
+    """Weighted degree d_i = sum_j w_ij (the diagonal of L_C, Eq. 2 weighted),
+    the exact sum rounded once (math.fsum), so no summation order enters."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    if w is None:
+        return np.diff(rowptr).astype(np.float64)
+    ww = np.asarray(w, dtype=np.float64)
+    return np.array([math.fsum(ww[rowptr[i]:rowptr[i + 1]].tolist())
+                     for i in range(rowptr.size - 1)], dtype=np.float64)
 
 
 def pattern_degrees(rowptr):

@@ -1,0 +1,798 @@
+// C ABI and the host-side LOBPCG driver (Algorithm 1) of the partitioner
+// (Algorithm 2).  Everything is ordered on the handle's stream; the only
+// per-iteration host/device exchange is one small status read.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "kernels.h"
+
+using namespace sphx;
+
+namespace {
+
+const char *kStatusText[] = {
+    "ok", "invalid argument", "malformed CSR graph", "graph not symmetric",
+    "bad weight", "self-loop", "Rayleigh-Ritz breakdown", "HIP error",
+    "workspace too small or allocation failed"};
+
+int bytes_of(int dtype) { return dtype == SPHX_F32 ? 4 : 8; }
+
+// Workspace: the caller's if large enough, else an owned (cached) one.
+int get_workspace(sphx_handle *h, size_t need, char **out) {
+  if (h->ws_user && h->ws_user_bytes >= need) {
+    *out = static_cast<char *>(h->ws_user);
+    return SPHX_OK;
+  }
+  if (h->ws_own_bytes < need) {
+    if (h->ws_own) (void)hipFree(h->ws_own);
+    h->ws_own = nullptr;
+    h->ws_own_bytes = 0;
+    if (hipMalloc(&h->ws_own, need) != hipSuccess)
+      return set_err(h, SPHX_E_WORKSPACE, "workspace allocation failed");
+    h->ws_own_bytes = need;
+  }
+  *out = static_cast<char *>(h->ws_own);
+  return SPHX_OK;
+}
+
+constexpr int kDegBlocksMax = 1024;
+constexpr int kRqBlocks = 256;
+
+// Workspace layout of a solve (also used for sizing with count_only).
+template <typename T>
+struct SolveWs {
+  double *d64, *dinv;
+  T *X, *LX, *R, *B1, *B2, *LH, *P, *LP;
+  double *X64, *LX64;
+  double *norm_partials, *gram_partials, *gram_out, *Y, *theta;
+  DevStatus *status;
+  double *rq_partials, *rq_sums, *res_sums;
+  void *norm_scratch;
+  double *deg_scratch;
+  int *flags;
+  void *split_scratch, *quality_scratch;
+  T *V;        // eigenvectors when the caller passes none (partition)
+  int32_t *part;
+  SpmmPlan plan;
+  size_t plan_off;
+};
+
+template <typename T>
+void layout(Arena &a, SolveWs<T> &w, int64_t n, int m, int K, size_t plan_b,
+            bool want_split) {
+  w.d64 = a.take<double>(n);
+  w.dinv = a.take<double>(n);
+  size_t blk = (size_t)n * m;
+  w.X = a.take<T>(blk);
+  w.LX = a.take<T>(blk);
+  w.R = a.take<T>(blk);
+  w.B1 = a.take<T>(blk);
+  w.B2 = a.take<T>(blk);
+  w.LH = a.take<T>(blk);
+  w.P = a.take<T>(blk);
+  w.LP = a.take<T>(blk);
+  if (std::is_same_v<T, float>) {
+    w.X64 = a.take<double>(blk);
+    w.LX64 = a.take<double>(blk);
+  } else {
+    w.X64 = w.LX64 = nullptr;
+  }
+  w.norm_partials = a.take<double>((size_t)kMaxNormBlocks * 2 * kMaxNev);
+  w.gram_partials = a.take<double>(gram_partial_doubles(kGramBlocks));
+  w.gram_out = a.take<double>(2 * kMaxW * kMaxW);
+  w.Y = a.take<double>(kMaxW * kMaxNev);
+  w.theta = a.take<double>(kMaxNev);
+  w.status = a.take<DevStatus>(1);
+  w.rq_partials = a.take<double>((size_t)kRqBlocks * 2 * kMaxNev);
+  w.rq_sums = a.take<double>(2 * kMaxNev);
+  w.res_sums = a.take<double>(2 * kMaxNev);
+  w.norm_scratch = a.take<char>(normalize_scratch_bytes());
+  w.deg_scratch = a.take<double>(4 * kDegBlocksMax);
+  w.flags = a.take<int>(64);
+  if (want_split) {
+    w.split_scratch = a.take<char>(split_scratch_bytes(n, K));
+    w.quality_scratch = a.take<char>(quality_scratch_bytes(K));
+    w.V = a.take<T>(blk);
+    w.part = a.take<int32_t>(n);
+  } else {
+    w.split_scratch = w.quality_scratch = nullptr;
+    w.V = nullptr;
+    w.part = nullptr;
+  }
+  w.plan_off = a.off;
+  a.off += plan_b;
+}
+
+bool valid_options(const sphx_options *o) {
+  if (!o) return false;
+  if (o->problem != SPHX_COMBINATORIAL && o->problem != SPHX_GENERALIZED) return false;
+  if (o->precond < SPHX_PRECOND_NONE || o->precond > SPHX_PRECOND_CHEBYSHEV) return false;
+  if (o->precond == SPHX_PRECOND_CHEBYSHEV && (o->cheb_degree < 1 || !(o->cheb_ratio > 1.0)))
+    return false;
+  if (o->precision != SPHX_FP64 && o->precision != SPHX_MIXED) return false;
+  if (!(o->tol > 0.0) || o->max_iter < 0) return false;
+  if (o->init < SPHX_INIT_RANDOM || o->init > SPHX_INIT_USER) return false;
+  if (o->drop_tol < 0.0) return false;
+  return true;
+}
+
+ColMap identity_map(int m) {
+  ColMap c;
+  c.count = m;
+  for (int i = 0; i < kMaxNev; ++i) c.col[i] = i < m ? i : 0;
+  return c;
+}
+
+__global__ void k_inverse(const double *d, double *dinv, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dinv[i] = 1.0 / d[i];
+}
+
+template <typename T>
+__global__ void k_jacobi(const T *R, const double *d, T *H, int64_t n, int m) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * m;
+       e += (int64_t)gridDim.x * blockDim.x)
+    H[e] = T(double(R[e]) / d[e / m]);
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool on = false;
+  void start(hipStream_t s) {
+    if (!a) { (void)hipEventCreate(&a); (void)hipEventCreate(&b); }
+    (void)hipEventRecord(a, s);
+    on = true;
+  }
+  double stop(hipStream_t s) {
+    if (!on) return 0.0;
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+  }
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// Chebyshev step coefficients (Chebyshev iteration for L h = r on [lo, hi]).
+struct ChebCoef {
+  double c, e;
+  std::vector<double> alpha, beta;
+};
+ChebCoef cheb_coef(int degree, double lo, double hi) {
+  ChebCoef k;
+  k.c = 0.5 * (hi + lo);
+  k.e = 0.5 * (hi - lo);
+  double sigma = k.c / k.e;
+  double rho_prev = 1.0 / sigma;
+  for (int s = 0; s < degree; ++s) {
+    double rho = 1.0 / (2.0 * sigma - rho_prev);
+    k.alpha.push_back(rho * rho_prev);
+    k.beta.push_back(2.0 * rho / k.e);
+    rho_prev = rho;
+  }
+  return k;
+}
+
+// H[:, cm] = p(L) R[:, cm]: returns the buffer holding the result.
+template <typename T>
+int cheb_apply(sphx_graph *g, const SpmmPlan &plan, int m, const ColMap &cm, const T *R,
+               T *B1, T *B2, const ChebCoef &k, const double *dinv, hipStream_t s,
+               T **result, int64_t *calls) {
+  // step 1 gathers h1 = r / c from R directly; h0 = 0
+  auto epi = [&](const T *prev, double prev_scale, T *out, double src_scale, int st) {
+    EpiChebP<T> e;
+    e.prev = prev;
+    e.R = R;
+    e.OUT = out;
+    e.ld = m;
+    e.src_scale = src_scale;
+    e.prev_scale = prev_scale;
+    e.alpha = k.alpha[st];
+    e.beta = k.beta[st];
+    e.dinv = dinv;
+    return e;
+  };
+  SPHX_TRY(spmm_cheb<T>(g, plan, R, m, cm, epi(nullptr, 1.0, B1, 1.0 / k.c, 0), s));
+  ++*calls;
+  T *cur = B1, *other = B2;
+  const int deg = (int)k.alpha.size();
+  if (deg >= 2) {
+    // step 2: the previous iterate h1 = r / c is read from R with a scale
+    SPHX_TRY(spmm_cheb<T>(g, plan, B1, m, cm, epi(R, 1.0 / k.c, B2, 1.0, 1), s));
+    ++*calls;
+    cur = B2;
+    other = B1;
+    // later steps overwrite the older iterate in place (each element is read
+    // and written by the same lane only)
+    for (int st = 2; st < deg; ++st) {
+      SPHX_TRY(spmm_cheb<T>(g, plan, cur, m, cm, epi(other, 1.0, other, 1.0, st), s));
+      ++*calls;
+      std::swap(cur, other);
+    }
+  }
+  *result = cur;
+  return SPHX_OK;
+}
+
+// The LOBPCG solve (Algorithm 1) in precision T; fills eigvals / vecs.
+template <typename T>
+int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const void *X0,
+          double *eigvals, T *vecs_out, sphx_stats *stats, SolveWs<T> &w, char *wsbase,
+          bool *hit_max) {
+  hipStream_t s = h->stream;
+  const int64_t n = g->n;
+  int64_t calls = 0;
+  Timer tall;
+  tall.start(s);
+  // ---- setup: degrees, classification, row bins
+  DegreeStats ds;
+  SPHX_TRY(compute_degrees(g, w.d64, nullptr, w.deg_scratch, &ds, h->pinned_small, s));
+  const bool gen = o.problem == SPHX_GENERALIZED;
+  if ((gen || o.precond == SPHX_PRECOND_JACOBI) && !(ds.min_wdeg > 0.0))
+    return set_err(h, SPHX_E_INVALID_ARG,
+                   "isolated vertex: the generalized problem and Jacobi need all degrees > 0");
+  Arena pa;
+  pa.base = wsbase + w.plan_off;
+  pa.cap = plan_bytes(g);
+  SPHX_TRY(build_plan(g, pa, &w.plan, ds, h->pinned_small, s));
+  const double *bdiag = gen ? w.d64 : nullptr;
+  const double *dinv = nullptr;
+  ChebCoef ck;
+  if (o.precond == SPHX_PRECOND_CHEBYSHEV) {
+    double hi = gen ? 2.0 : 2.0 * ds.max_wdeg;
+    ck = cheb_coef(o.cheb_degree, hi / o.cheb_ratio, hi);
+    if (gen) {
+      hipLaunchKernelGGL(k_inverse, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, w.d64,
+                         w.dinv, n);
+      dinv = w.dinv;
+    }
+  }
+  if (stats) {
+    stats->max_degree = ds.max_deg;
+    stats->avg_degree = n ? double(ds.sum_deg) / double(n) : 0.0;
+    stats->graph_regular = (ds.max_deg * n <= 10 * ds.sum_deg) ? 1 : 0;
+  }
+  const double drop = o.drop_tol > 0 ? o.drop_tol
+                                     : (std::is_same_v<T, float> ? 1e-10 : 1e-14);
+  const ColMap idm = identity_map(m);
+  DevStatus *hs = h->pinned_status;
+  // ---- initial block and Rayleigh-Ritz
+  if (o.init == SPHX_INIT_USER)
+    SPHX_HIP(h, hipMemcpyAsync(w.X, X0, sizeof(T) * n * m, hipMemcpyDeviceToDevice, s));
+  else if (o.init == SPHX_INIT_PIECEWISE)
+    launch_init_piecewise<T>(w.X, n, m, s);
+  else
+    launch_init_random<T>(w.X, n, m, o.seed, s);
+  SPHX_TRY(spmm_store<T>(g, w.plan, w.X, m, idm, EpiStoreP<T>{w.LX, m}, s));
+  ++calls;
+  GramArgs ga{n, m, idm, 0, 0, bdiag};
+  ga.act.count = 0;
+  SPHX_TRY(gram<T>(w.X, w.LX, nullptr, nullptr, nullptr, nullptr, ga, w.gram_partials,
+                   kGramBlocks, w.gram_out, s));
+  launch_rr(w.gram_out, RRArgs{m, m, m, drop}, w.Y, w.theta, w.status, s);
+  UpdateArgs ua{n, m, idm, 0, 0};
+  ua.act.count = 0;
+  launch_update<T>(w.X, nullptr, w.P, nullptr, w.LP, w.Y, ua, s);
+  const bool jac = o.precond == SPHX_PRECOND_JACOBI;
+  auto residual = [&]() -> int {
+    int nb = 0;
+    EpiResidualP<T> er{w.LX, jac ? w.B1 : w.R, m, w.theta, w.d64, gen ? 1 : 0, jac ? 1 : 0};
+    SPHX_TRY(spmm_residual<T>(g, w.plan, w.X, m, idm, er, w.norm_partials, &nb, s));
+    ++calls;
+    launch_finalize(w.norm_partials, nb, m, w.theta, o.tol, o.locking, w.status, s);
+    SPHX_HIP(h, hipMemcpyAsync(hs, w.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    SPHX_HIP(h, hipStreamSynchronize(s));
+    return SPHX_OK;
+  };
+  SPHX_TRY(residual());
+  if (hs->breakdown)
+    return set_err(h, SPHX_E_BREAKDOWN, "initial block is rank deficient");
+  // ---- iterations
+  int it = 0, restarts = 0;
+  bool have_p = false;
+  while (hs->nact > 0 && it < o.max_iter) {
+    ColMap act;
+    act.count = hs->nact;
+    for (int q = 0; q < kMaxNev; ++q) act.col[q] = q < hs->nact ? hs->act[q] : 0;
+    T *H = w.B1;
+    if (o.precond == SPHX_PRECOND_CHEBYSHEV) {
+      SPHX_TRY(cheb_apply<T>(g, w.plan, m, act, w.R, w.B1, w.B2, ck, dinv, s, &H, &calls));
+    } else if (o.precond == SPHX_PRECOND_NONE) {
+      H = w.R;
+    }
+    SPHX_TRY(spmm_store<T>(g, w.plan, H, m, act, EpiStoreP<T>{w.LH, m}, s));
+    ++calls;
+    GramArgs gb{n, m, act, 1, have_p ? 1 : 0, bdiag};
+    SPHX_TRY(gram<T>(w.X, w.LX, H, w.LH, w.P, w.LP, gb, w.gram_partials, kGramBlocks,
+                     w.gram_out, s));
+    const int na = act.count;
+    const int wdt = m + na + (have_p ? na : 0);
+    launch_rr(w.gram_out, RRArgs{m, wdt, have_p ? m + na : wdt, drop}, w.Y, w.theta,
+              w.status, s);
+    UpdateArgs ub{n, m, act, 1, have_p ? 1 : 0};
+    launch_update<T>(w.X, H, w.P, w.LH, w.LP, w.Y, ub, s);
+    have_p = true;
+    // Jacobi writes the next H into B1, which held this iteration's H (consumed
+    // by the update above); Chebyshev and no preconditioner write R.
+    SPHX_TRY(residual());
+    ++it;
+    restarts += hs->restarted;
+    if (hs->breakdown)
+      return set_err(h, SPHX_E_BREAKDOWN,
+                     "Rayleigh-Ritz basis rank deficient even without the P block");
+  }
+  *hit_max = hs->nact > 0;
+  // ---- final FP64 residual check and normalisation
+  double *X64 = reinterpret_cast<double *>(w.X);
+  double *LX64 = reinterpret_cast<double *>(w.LX);
+  if constexpr (std::is_same_v<T, float>) {
+    launch_convert<float, double>(w.X, w.X64, n * m, s);
+    X64 = w.X64;
+    LX64 = w.LX64;
+    SPHX_TRY(spmm_store<double>(g, w.plan, X64, m, idm, EpiStoreP<double>{LX64, m}, s));
+    ++calls;
+  }
+  int rb = (int)grid_for(n, 256 / m, kRqBlocks);
+  launch_rq_partials<double>(X64, LX64, n, m, bdiag, w.rq_partials, rb, s);
+  launch_sum_partials(w.rq_partials, rb, m, w.rq_sums, s);
+  double sums[2 * kMaxNev];
+  SPHX_HIP(h, hipMemcpyAsync(sums, w.rq_sums, sizeof(sums), hipMemcpyDeviceToHost, s));
+  SPHX_HIP(h, hipStreamSynchronize(s));
+  double th[kMaxNev];
+  for (int c = 0; c < m; ++c) th[c] = sums[kMaxNev + c] > 0 ? sums[c] / sums[kMaxNev + c] : 0;
+  SPHX_HIP(h, hipMemcpyAsync(w.theta, th, sizeof(double) * m, hipMemcpyHostToDevice, s));
+  launch_res_partials<double>(X64, LX64, n, m, bdiag, w.theta, w.rq_partials, rb, s);
+  launch_sum_partials(w.rq_partials, rb, m, w.res_sums, s);
+  double rs[2 * kMaxNev];
+  SPHX_HIP(h, hipMemcpyAsync(rs, w.res_sums, sizeof(rs), hipMemcpyDeviceToHost, s));
+  SPHX_HIP(h, hipStreamSynchronize(s));
+  // ascending order of the Rayleigh quotients
+  std::vector<int> perm(m);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return th[a] < th[b]; });
+  double floor_th = m > 1 ? th[perm[1]] : th[perm[0]];
+  double scale[kMaxNev];
+  int nconv = 0;
+  for (int q = 0; q < m; ++q) {
+    int c = perm[q];
+    eigvals[q] = th[c];
+    double sc = std::max(th[c], floor_th);
+    if (!(sc > 0)) sc = 1.0;
+    double rho = rs[kMaxNev + c] > 0 ? std::sqrt(rs[c]) / (sc * std::sqrt(rs[kMaxNev + c]))
+                                     : INFINITY;
+    if (stats && q < 32) stats->rho[q] = rho;
+    if (rho <= o.tol) ++nconv;
+    scale[q] = rs[kMaxNev + c] > 0 ? 1.0 / std::sqrt(rs[kMaxNev + c]) : 1.0;
+  }
+  for (int q = 0; q < m; ++q)
+    launch_copy_cols<T>(w.X + perm[q], m, vecs_out + q, m, n, 1, s);
+  SPHX_TRY(normalize_columns<T>(vecs_out, n, m, scale, w.norm_scratch, s));
+  if (stats) {
+    stats->iterations = it;
+    stats->converged = nconv;
+    stats->restarts = restarts;
+    stats->spmm_calls = calls;
+    stats->ms_total = tall.stop(s);
+  } else {
+    SPHX_HIP(h, hipStreamSynchronize(s));
+  }
+  return SPHX_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char *sphx_status_string(int status) {
+  if (status == SPHX_NOT_CONVERGED) return "not converged (max_iter reached)";
+  if (status <= 0 && status >= -8) return kStatusText[-status];
+  return "unknown status";
+}
+
+int sphx_create(sphx_handle **out, int device, void *stream) {
+  if (!out) return SPHX_E_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return SPHX_E_INVALID_ARG;
+  auto *h = new sphx_handle();
+  h->device = device;
+  h->stream = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc((void **)&h->pinned_status, sizeof(DevStatus)) != hipSuccess ||
+      hipHostMalloc(&h->pinned_small, 65536) != hipSuccess) {
+    delete h;
+    return SPHX_E_HIP;
+  }
+  *out = h;
+  return SPHX_OK;
+}
+
+int sphx_destroy(sphx_handle *h) {
+  if (!h) return SPHX_E_INVALID_ARG;
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  if (h->ws_own) (void)hipFree(h->ws_own);
+  if (h->pinned_status) (void)hipHostFree(h->pinned_status);
+  if (h->pinned_small) (void)hipHostFree(h->pinned_small);
+  delete h;
+  return SPHX_OK;
+}
+
+int sphx_set_stream(sphx_handle *h, void *stream) {
+  if (!h) return SPHX_E_INVALID_ARG;
+  h->stream = static_cast<hipStream_t>(stream);
+  return SPHX_OK;
+}
+
+const char *sphx_last_error(const sphx_handle *h) { return h ? h->err.c_str() : ""; }
+
+int sphx_set_timing(sphx_handle *h, int on) {
+  if (!h) return SPHX_E_INVALID_ARG;
+  h->timing = on ? 1 : 0;
+  return SPHX_OK;
+}
+
+int sphx_num_eigenvectors(int K) {
+  if (K < 1) return -1;
+  int d = 0;
+  while (K) { ++d; K >>= 1; }
+  return d;
+}
+
+void sphx_options_default(sphx_options *o, int regular, int precond) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precond = precond;
+  o->problem = regular ? SPHX_COMBINATORIAL : SPHX_GENERALIZED;
+  o->tol = regular ? 1e-3 : 1e-2;
+  o->init = regular ? SPHX_INIT_RANDOM : SPHX_INIT_PIECEWISE;
+  o->cheb_degree = 25;
+  o->cheb_ratio = 100.0;
+  o->precision = SPHX_FP64;
+  o->max_iter = 10000;
+  o->seed = 0x5eed;
+  o->locking = 1;
+  o->drop_tol = 0.0;
+}
+
+int sphx_graph_create(sphx_handle *h, int64_t n, int64_t nnz, const void *row_ptr,
+                      int row_ptr_is_64, const int32_t *col, const void *w, int w_dtype,
+                      const int32_t *vwgt, uint32_t flags, sphx_graph **out) {
+  if (!h || !out) return SPHX_E_INVALID_ARG;
+  *out = nullptr;
+  if (n < 1 || n >= (int64_t(1) << 31) || nnz < 0 || !row_ptr || (nnz > 0 && !col))
+    return set_err(h, SPHX_E_INVALID_ARG, "bad sizes or null pointers");
+  if (!row_ptr_is_64 && nnz >= (int64_t(1) << 31))
+    return set_err(h, SPHX_E_INVALID_ARG, "nnz needs an int64 row_ptr");
+  if (w_dtype != SPHX_UNIT && w_dtype != SPHX_F32 && w_dtype != SPHX_F64)
+    return set_err(h, SPHX_E_INVALID_ARG, "bad weight dtype");
+  if ((w_dtype == SPHX_UNIT) != (w == nullptr))
+    return set_err(h, SPHX_E_INVALID_ARG, "weights pointer and dtype disagree");
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  auto *g = new sphx_graph();
+  g->h = h;
+  g->n = n;
+  g->nnz = nnz;
+  g->rowptr = row_ptr;
+  g->rp64 = row_ptr_is_64 ? 1 : 0;
+  g->col = col;
+  g->w = w;
+  g->wdt = w_dtype;
+  g->vwgt = vwgt;
+  if (!(flags & SPHX_SKIP_VALIDATE)) {
+    int32_t *fd = nullptr;
+    if (hipMallocAsync((void **)&fd, 256, h->stream) != hipSuccess) {
+      delete g;
+      return SPHX_E_HIP;
+    }
+    int st = validate_graph(g, h->stream, fd, static_cast<int *>(h->pinned_small));
+    (void)hipFreeAsync(fd, h->stream);
+    (void)hipStreamSynchronize(h->stream);
+    if (st != SPHX_OK) {
+      delete g;
+      return st;
+    }
+  }
+  *out = g;
+  return SPHX_OK;
+}
+
+int sphx_graph_destroy(sphx_graph *g) {
+  if (!g) return SPHX_E_INVALID_ARG;
+  delete g;
+  return SPHX_OK;
+}
+
+int sphx_graph_info(sphx_handle *h, sphx_graph *g, int *is_regular, int64_t *max_degree,
+                    double *avg_degree) {
+  if (!h || !g) return SPHX_E_INVALID_ARG;
+  size_t need = align_up(sizeof(double) * g->n, 256) + 4 * kDegBlocksMax * sizeof(double) + 512;
+  char *ws = nullptr;
+  SPHX_TRY(get_workspace(h, need, &ws));
+  DegreeStats ds;
+  SPHX_TRY(compute_degrees(g, reinterpret_cast<double *>(ws), nullptr,
+                           ws + align_up(sizeof(double) * g->n, 256), &ds, h->pinned_small,
+                           h->stream));
+  if (is_regular) *is_regular = (ds.max_deg * g->n <= 10 * ds.sum_deg) ? 1 : 0;
+  if (max_degree) *max_degree = ds.max_deg;
+  if (avg_degree) *avg_degree = double(ds.sum_deg) / double(g->n);
+  return SPHX_OK;
+}
+
+static size_t solve_bytes(sphx_graph *g, int nev, int precision, int K, bool split) {
+  Arena a;
+  a.count_only = true;
+  size_t pb = plan_bytes(g);
+  if (precision == SPHX_MIXED) {
+    SolveWs<float> w;
+    layout(a, w, g->n, nev, K, pb, split);
+  } else {
+    SolveWs<double> w;
+    layout(a, w, g->n, nev, K, pb, split);
+  }
+  return a.off + 4096;
+}
+
+int sphx_workspace_size(sphx_handle *h, sphx_graph *g, int nev, const sphx_options *opt,
+                        size_t *bytes) {
+  if (!h || !g || !opt || !bytes || nev < 1 || nev > kMaxNev) return SPHX_E_INVALID_ARG;
+  int K = 1 << (nev - 1);
+  size_t a = solve_bytes(g, nev, opt->precision, K, true);
+  size_t b = adjoint_scratch_bytes(g->n, nev) + plan_bytes(g) + sizeof(double) * 2 * g->n +
+             4096;
+  *bytes = std::max(a, b);
+  return SPHX_OK;
+}
+
+int sphx_set_workspace(sphx_handle *h, void *ptr, size_t bytes) {
+  if (!h) return SPHX_E_INVALID_ARG;
+  h->ws_user = ptr;
+  h->ws_user_bytes = ptr ? bytes : 0;
+  return SPHX_OK;
+}
+
+int sphx_laplacian_apply(sphx_handle *h, sphx_graph *g, int m, int dtype, const void *X,
+                         void *Y) {
+  if (!h || !g || !X || !Y || m < 1 || m > kMaxNev ||
+      (dtype != SPHX_F32 && dtype != SPHX_F64))
+    return SPHX_E_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  char *ws = nullptr;
+  size_t need = plan_bytes(g) + align_up(sizeof(double) * g->n, 256) +
+                4 * kDegBlocksMax * sizeof(double) + 1024;
+  SPHX_TRY(get_workspace(h, need, &ws));
+  DegreeStats ds;
+  double *d64 = reinterpret_cast<double *>(ws);
+  char *rest = ws + align_up(sizeof(double) * g->n, 256);
+  SPHX_TRY(compute_degrees(g, d64, nullptr, rest, &ds, h->pinned_small, h->stream));
+  Arena pa;
+  pa.base = rest + align_up(4 * kDegBlocksMax * sizeof(double), 256);
+  SpmmPlan plan;
+  SPHX_TRY(build_plan(g, pa, &plan, ds, h->pinned_small, h->stream));
+  ColMap cm = identity_map(m);
+  if (dtype == SPHX_F32)
+    return spmm_store<float>(g, plan, (const float *)X, m, cm,
+                             EpiStoreP<float>{(float *)Y, m}, h->stream);
+  return spmm_store<double>(g, plan, (const double *)X, m, cm,
+                            EpiStoreP<double>{(double *)Y, m}, h->stream);
+}
+
+int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int m,
+                       int dtype, const void *R, void *H) {
+  if (!h || !g || !valid_options(o) || !R || !H || m < 1 || m > kMaxNev ||
+      (dtype != SPHX_F32 && dtype != SPHX_F64))
+    return SPHX_E_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  hipStream_t s = h->stream;
+  size_t blk = (size_t)g->n * m * bytes_of(dtype);
+  size_t need = plan_bytes(g) + 2 * align_up(sizeof(double) * g->n, 256) +
+                2 * align_up(blk, 256) + 4 * kDegBlocksMax * sizeof(double) + 4096;
+  char *ws = nullptr;
+  SPHX_TRY(get_workspace(h, need, &ws));
+  Arena a;
+  a.base = ws;
+  double *d64 = a.take<double>(g->n);
+  double *dinv = a.take<double>(g->n);
+  double *degs = a.take<double>(4 * kDegBlocksMax);
+  char *b1 = a.take<char>(blk);
+  char *b2 = a.take<char>(blk);
+  DegreeStats ds;
+  SPHX_TRY(compute_degrees(g, d64, nullptr, degs, &ds, h->pinned_small, s));
+  SpmmPlan plan;
+  SPHX_TRY(build_plan(g, a, &plan, ds, h->pinned_small, s));
+  const int64_t n = g->n;
+  if (o->precond == SPHX_PRECOND_NONE) {
+    SPHX_HIP(h, hipMemcpyAsync(H, R, blk, hipMemcpyDeviceToDevice, s));
+  } else if (o->precond == SPHX_PRECOND_JACOBI) {
+    if (!(ds.min_wdeg > 0)) return set_err(h, SPHX_E_INVALID_ARG, "isolated vertex");
+    if (dtype == SPHX_F32)
+      hipLaunchKernelGGL(k_jacobi<float>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s,
+                         (const float *)R, d64, (float *)H, n, m);
+    else
+      hipLaunchKernelGGL(k_jacobi<double>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s,
+                         (const double *)R, d64, (double *)H, n, m);
+  } else {
+    const bool gen = o->problem == SPHX_GENERALIZED;
+    if (gen && !(ds.min_wdeg > 0)) return set_err(h, SPHX_E_INVALID_ARG, "isolated vertex");
+    double hi = gen ? 2.0 : 2.0 * ds.max_wdeg;
+    ChebCoef ck = cheb_coef(o->cheb_degree, hi / o->cheb_ratio, hi);
+    const double *dv = nullptr;
+    if (gen) {
+      hipLaunchKernelGGL(k_inverse, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, d64, dinv, n);
+      dv = dinv;
+    }
+    ColMap cm = identity_map(m);
+    int64_t calls = 0;
+    if (dtype == SPHX_F32) {
+      float *res = nullptr;
+      SPHX_TRY(cheb_apply<float>(g, plan, m, cm, (const float *)R, (float *)b1, (float *)b2,
+                                 ck, dv, s, &res, &calls));
+      SPHX_HIP(h, hipMemcpyAsync(H, res, blk, hipMemcpyDeviceToDevice, s));
+    } else {
+      double *res = nullptr;
+      SPHX_TRY(cheb_apply<double>(g, plan, m, cm, (const double *)R, (double *)b1,
+                                  (double *)b2, ck, dv, s, &res, &calls));
+      SPHX_HIP(h, hipMemcpyAsync(H, res, blk, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  SPHX_HIP(h, hipGetLastError());
+  return SPHX_OK;
+}
+
+static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_options *o,
+                           const void *X0, double *eigvals, void *eigvecs, int K,
+                           int32_t *part, double *cut, double *imbalance,
+                           sphx_stats *stats) {
+  if (!h || !g || !valid_options(o) || !eigvals) return SPHX_E_INVALID_ARG;
+  if (nev < 1 || nev > kMaxNev || nev >= g->n)
+    return set_err(h, SPHX_E_INVALID_ARG, "need 1 <= nev <= 16 and nev < n");
+  if (o->init == SPHX_INIT_USER && !X0)
+    return set_err(h, SPHX_E_INVALID_ARG, "SPHX_INIT_USER needs X0");
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  const bool split = part != nullptr;
+  char *ws = nullptr;
+  SPHX_TRY(get_workspace(h, solve_bytes(g, nev, o->precision, std::max(K, 1), split), &ws));
+  bool hit_max = false;
+  int st;
+  auto run = [&](auto tag) -> int {
+    using T = decltype(tag);
+    Arena a;
+    a.base = ws;
+    SolveWs<T> w;
+    layout(a, w, g->n, nev, std::max(K, 1), plan_bytes(g), split);
+    T *vecs = eigvecs ? static_cast<T *>(eigvecs) : w.V;
+    if (!vecs) return set_err(h, SPHX_E_INVALID_ARG, "eigvecs is NULL");
+    SPHX_TRY(solve<T>(h, g, nev, *o, X0, eigvals, vecs, stats, w, ws, &hit_max));
+    if (split) {
+      Timer ts;
+      if (stats) ts.start(h->stream);
+      std::string err;
+      int r = split_pow2<T>(g, vecs + 1, nev, nev - 1, K, part, w.split_scratch,
+                            h->pinned_small, h->stream, &err);
+      if (r != SPHX_OK) return set_err(h, r, err);
+      if (stats) stats->ms_split = ts.stop(h->stream);
+      Timer tq;
+      if (stats) tq.start(h->stream);
+      r = quality(g, part, K, cut, imbalance, nullptr, w.quality_scratch, h->pinned_small,
+                  h->stream, &err);
+      if (r != SPHX_OK) return set_err(h, r, err);
+      if (stats) {
+        stats->ms_quality = tq.stop(h->stream);
+        stats->ms_total += stats->ms_split + stats->ms_quality;
+      }
+    }
+    return SPHX_OK;
+  };
+  st = o->precision == SPHX_MIXED ? run(float{}) : run(double{});
+  if (st < 0) return st;
+  return hit_max ? SPHX_NOT_CONVERGED : SPHX_OK;
+}
+
+int sphx_eigensolve(sphx_handle *h, sphx_graph *g, int nev, const sphx_options *o,
+                    const void *X0, double *eigvals, void *eigvecs, sphx_stats *stats) {
+  if (!eigvecs) return SPHX_E_INVALID_ARG;
+  return eigensolve_impl(h, g, nev, o, X0, eigvals, eigvecs, 1, nullptr, nullptr, nullptr,
+                         stats);
+}
+
+int sphx_partition(sphx_handle *h, sphx_graph *g, int K, const sphx_options *o,
+                   const void *X0, double *eigvals, void *eigvecs, int32_t *part,
+                   double *cut, double *imbalance, sphx_stats *stats) {
+  if (!h || !g || !part) return SPHX_E_INVALID_ARG;
+  if (K < 2 || (K & (K - 1)) != 0 || K > g->n)
+    return set_err(h, SPHX_E_INVALID_ARG, "K must be a power of two with 2 <= K <= n");
+  int d = sphx_num_eigenvectors(K);
+  if (d > kMaxNev) return set_err(h, SPHX_E_INVALID_ARG, "K too large (d > 16)");
+  return eigensolve_impl(h, g, d, o, X0, eigvals, eigvecs, K, part, cut, imbalance, stats);
+}
+
+int sphx_split(sphx_handle *h, sphx_graph *g, const void *coords, int ld, int ncoord,
+               int dtype, int K, int32_t *part) {
+  if (!h || !g || !coords || !part || ncoord < 1 || ld < ncoord ||
+      (dtype != SPHX_F32 && dtype != SPHX_F64))
+    return SPHX_E_INVALID_ARG;
+  if (K < 1 || (K & (K - 1)) != 0 || K > (1 << 30) || K > g->n)
+    return set_err(h, SPHX_E_INVALID_ARG, "K must be a power of two, 1 <= K <= n");
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  char *ws = nullptr;
+  SPHX_TRY(get_workspace(h, split_scratch_bytes(g->n, K), &ws));
+  std::string err;
+  int r = dtype == SPHX_F32
+              ? split_pow2<float>(g, (const float *)coords, ld, ncoord, K, part, ws,
+                                  h->pinned_small, h->stream, &err)
+              : split_pow2<double>(g, (const double *)coords, ld, ncoord, K, part, ws,
+                                   h->pinned_small, h->stream, &err);
+  if (r != SPHX_OK) return set_err(h, r, err);
+  return SPHX_OK;
+}
+
+int sphx_quality(sphx_handle *h, sphx_graph *g, const int32_t *part, int K, double *cut,
+                 double *cut2x, double *imbalance, int64_t *part_weights) {
+  if (!h || !g || !part || K < 1) return SPHX_E_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  if (g->wdt != SPHX_UNIT && !g->stats_valid) {
+    size_t need = align_up(sizeof(double) * g->n, 256) + 4 * kDegBlocksMax * sizeof(double) + 512;
+    char *ws = nullptr;
+    SPHX_TRY(get_workspace(h, need, &ws));
+    DegreeStats ds;
+    SPHX_TRY(compute_degrees(g, reinterpret_cast<double *>(ws), nullptr,
+                             ws + align_up(sizeof(double) * g->n, 256), &ds, h->pinned_small,
+                             h->stream));
+  }
+  char *ws = nullptr;
+  SPHX_TRY(get_workspace(h, quality_scratch_bytes(K), &ws));
+  std::string err;
+  double c = 0.0;
+  int r = quality(g, part, K, &c, imbalance, part_weights, ws, h->pinned_small, h->stream, &err);
+  if (r != SPHX_OK) return set_err(h, r, err);
+  if (cut) *cut = c;
+  if (cut2x) *cut2x = 2.0 * c;
+  return SPHX_OK;
+}
+
+int sphx_eig_backward(sphx_handle *h, sphx_graph *g, int problem, int nev,
+                      const double *eigvals, const void *eigvecs, const double *g_vals,
+                      const void *g_vecs, double cg_tol, int cg_max_iter, void *grad_w) {
+  if (!h || !g || !eigvals || !eigvecs || !grad_w || nev < 1 || nev > kMaxNev ||
+      nev >= g->n || !(cg_tol > 0) || cg_max_iter < 1 ||
+      (problem != SPHX_COMBINATORIAL && problem != SPHX_GENERALIZED))
+    return SPHX_E_INVALID_ARG;
+  if (g->wdt == SPHX_F32)
+    return set_err(h, SPHX_E_INVALID_ARG, "the adjoint needs F64 (or unit) edge weights");
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  size_t need = adjoint_scratch_bytes(g->n, nev) + plan_bytes(g) +
+                align_up(sizeof(double) * g->n, 256) + 4 * kDegBlocksMax * sizeof(double) +
+                4096;
+  char *ws = nullptr;
+  SPHX_TRY(get_workspace(h, need, &ws));
+  Arena a;
+  a.base = ws;
+  double *d64 = a.take<double>(g->n);
+  double *degs = a.take<double>(4 * kDegBlocksMax);
+  DegreeStats ds;
+  SPHX_TRY(compute_degrees(g, d64, nullptr, degs, &ds, h->pinned_small, h->stream));
+  SpmmPlan plan;
+  SPHX_TRY(build_plan(g, a, &plan, ds, h->pinned_small, h->stream));
+  if (problem == SPHX_GENERALIZED && !(ds.min_wdeg > 0))
+    return set_err(h, SPHX_E_INVALID_ARG, "isolated vertex");
+  char *scratch = a.take<char>(adjoint_scratch_bytes(g->n, nev));
+  std::string err;
+  int r = eig_backward(g, plan, problem, nev, eigvals, (const double *)eigvecs, g_vals,
+                       (const double *)g_vecs, cg_tol, cg_max_iter, d64, (double *)grad_w,
+                       scratch, h->pinned_small, h->stream, &err);
+  if (r < 0) return set_err(h, r, err);
+  return r;
+}
+
+}  // extern "C"

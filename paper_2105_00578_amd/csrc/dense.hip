@@ -1,0 +1,815 @@
+// Dense block kernels of LOBPCG (Algorithm 1): initial blocks, Gram matrices
+// on FP64 matrix cores, Rayleigh-Ritz in one workgroup, the fused block
+// update, the convergence check, and final normalisation.
+//
+// Blocks are row-major n x m (ld = m).  The Rayleigh-Ritz basis is
+// S = [X, H_a, P_a] where a lists the active (unconverged) columns.
+#include <cmath>
+
+#include "kernels.h"
+
+namespace sphx {
+namespace {
+
+// ------------------------------------------------------------ random init
+// Counter-based normal draws: splitmix64 (Steele, Lea, Flood 2014) of the
+// element counter gives two uniforms, Box-Muller turns them into N(0, 1).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ void k_init_random(T *X, int64_t count, uint64_t seed) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t a = splitmix64(seed ^ splitmix64(2 * (uint64_t)e));
+    uint64_t b = splitmix64(seed ^ splitmix64(2 * (uint64_t)e + 1));
+    double u1 = (double)((a >> 11) + 1) * 0x1.0p-53;   // (0, 1]
+    double u2 = (double)(b >> 11) * 0x1.0p-53;         // [0, 1)
+    X[e] = T(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+  }
+}
+
+// Sec. 6.2.1: column 0 is the constant vector; column j >= 1 is the indicator
+// of index block j-1 of d blocks [floor(b n / d), floor((b+1) n / d)).
+template <typename T>
+__global__ void k_init_piecewise(T *X, int64_t n, int m) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = e / m;
+    int c = (int)(e - i * m);
+    T v = T(0);
+    if (c == 0) v = T(1);
+    else {
+      int64_t b = c - 1;
+      int64_t lo = b * n / m, hi = (b + 1) * n / m;
+      v = (i >= lo && i < hi) ? T(1) : T(0);
+    }
+    X[e] = v;
+  }
+}
+
+// ------------------------------------------------------------------ Gram
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kCh = 64;   // rows per LDS chunk
+
+struct GramDev {
+  int64_t n;
+  int m, w;
+  int offH, offP;           // column offsets of the H and P parts in S
+  int use_h, use_p;
+  int inv[kMaxNev];         // inverse active map: column -> position or -1
+  const double *bdiag;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_block(double *sS, int wp, const T *__restrict__ src,
+                                           int64_t r0, int64_t n, int m, int off,
+                                           const int *inv) {
+  const int total = kCh * m;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int row = e / m;
+    int col = e - row * m;
+    int pos = inv ? inv[col] : col;
+    if (pos < 0) continue;
+    int64_t gr = r0 + row;
+    double v = gr < n ? double(src[gr * m + col]) : 0.0;
+    sS[row * wp + off + pos] = v;
+  }
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void k_gram(GramDev a, const T *__restrict__ X,
+                                              const T *__restrict__ LX,
+                                              const T *__restrict__ H,
+                                              const T *__restrict__ LH,
+                                              const T *__restrict__ P,
+                                              const T *__restrict__ LP,
+                                              int64_t rows_per_block, double *partials) {
+  constexpr int W = 16 * NT;
+  constexpr int WP = W + 1;
+  constexpr int NTILES = NT * (NT + 1);   // upper tiles of both matrices
+  constexpr int TPW = (NTILES + 3) / 4;
+  __shared__ double sS[kCh * WP];
+  __shared__ double sL[kCh * WP];
+  __shared__ double sb[kCh];
+  __shared__ int sinv[kMaxNev];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  if (threadIdx.x < kMaxNev) sinv[threadIdx.x] = a.inv[threadIdx.x];
+  for (int e = threadIdx.x; e < kCh * WP; e += blockDim.x) {
+    sS[e] = 0.0;
+    sL[e] = 0.0;
+  }
+  // tile ownership
+  int tmat[TPW], tti[TPW], ttj[TPW];
+  d4 acc[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    int t = wave + 4 * q;
+    tmat[q] = -1;
+    tti[q] = ttj[q] = 0;
+    if (t < NTILES) {
+      int mat = t / (NT * (NT + 1) / 2);
+      int r = t % (NT * (NT + 1) / 2);
+      int ti = 0;
+      while (r >= NT - ti) { r -= NT - ti; ++ti; }
+      tmat[q] = mat;
+      tti[q] = ti;
+      ttj[q] = ti + r;
+    }
+    acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  __syncthreads();
+  const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t re = min(a.n, rb + rows_per_block);
+  const int i16 = lane & 15;
+  const int k4 = lane >> 4;
+  for (int64_t r0 = rb; r0 < re; r0 += kCh) {
+    load_block(sS, WP, X, r0, re, a.m, 0, (const int *)nullptr);
+    load_block(sL, WP, LX, r0, re, a.m, 0, (const int *)nullptr);
+    if (a.use_h) {
+      load_block(sS, WP, H, r0, re, a.m, a.offH, sinv);
+      load_block(sL, WP, LH, r0, re, a.m, a.offH, sinv);
+    }
+    if (a.use_p) {
+      load_block(sS, WP, P, r0, re, a.m, a.offP, sinv);
+      load_block(sL, WP, LP, r0, re, a.m, a.offP, sinv);
+    }
+    if (threadIdx.x < kCh) {
+      int64_t gr = r0 + threadIdx.x;
+      sb[threadIdx.x] = gr < re ? (a.bdiag ? a.bdiag[gr] : 1.0) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      if (tmat[q] < 0) continue;
+      const int ci = tti[q] * 16 + i16;
+      const int cj = ttj[q] * 16 + i16;
+      if (tmat[q] == 0) {
+#pragma unroll 4
+        for (int kk = 0; kk < kCh; kk += 4) {
+          int k = kk + k4;
+          double av = sS[k * WP + ci];
+          double bv = sL[k * WP + cj];
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+        }
+      } else {
+#pragma unroll 4
+        for (int kk = 0; kk < kCh; kk += 4) {
+          int k = kk + k4;
+          double av = sS[k * WP + ci];
+          double bv = sS[k * WP + cj] * sb[k];
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // D layout of the 16x16x4 FP64 product: lane holds rows 4*(lane/16)+r,
+  // column lane%16.
+  double *out = partials + (int64_t)blockIdx.x * 2 * W * W;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    if (tmat[q] < 0) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int gi = tti[q] * 16 + 4 * k4 + r;
+      int gj = ttj[q] * 16 + i16;
+      out[(int64_t)tmat[q] * W * W + gi * W + gj] = acc[q][r];
+    }
+  }
+}
+
+// Sum the block partials of upper tiles in block order.
+__global__ void k_gram_reduce(const double *partials, int nblocks, int NT, double *out) {
+  const int W = 16 * NT;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * W * W;
+       e += gridDim.x * blockDim.x) {
+    int mat = e / (W * W);
+    int ij = e - mat * W * W;
+    int i = ij / W, j = ij - i * W;
+    double s = 0.0;
+    if (i / 16 <= j / 16)
+      for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * 2 * W * W + e];
+    out[mat * kMaxW * kMaxW + i * kMaxW + j] = s;
+  }
+}
+
+// --------------------------------------------------------- Rayleigh-Ritz
+constexpr int LDA = kMaxW + 1;
+
+// Cyclic Jacobi eigensolver (round-robin parallel ordering) on the k x k
+// symmetric matrix A (LDS, stride LDA); V receives the eigenvectors.
+__device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
+                           int *pp, int *pq, int *changed) {
+  __shared__ double anorm;
+  const int t = threadIdx.x;
+  for (int e = t; e < k * k; e += blockDim.x) {
+    int i = e / k, j = e - i * k;
+    V[i * LDA + j] = (i == j) ? 1.0 : 0.0;
+  }
+  if (t == 0) {
+    double s = 0.0;
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) s += A[i * LDA + j] * A[i * LDA + j];
+    anorm = sqrt(s);
+  }
+  __syncthreads();
+  if (k < 2) return;
+  const double abs_floor = 1e-17 * anorm + 1e-300;
+  const int kk = k + (k & 1);
+  const int npair = kk / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (t == 0) *changed = 0;
+    __syncthreads();
+    for (int r = 0; r < kk - 1; ++r) {
+      if (t < npair) {
+        int p, q;
+        if (t == 0) { p = kk - 1; q = r; }
+        else { p = (r + t) % (kk - 1); q = (r - t + kk - 1) % (kk - 1); }
+        if (p > q) { int tmp = p; p = q; q = tmp; }
+        double c = 1.0, s = 0.0;
+        if (q < k) {
+          double apq = A[p * LDA + q];
+          double app = A[p * LDA + p], aqq = A[q * LDA + q];
+          if (fabs(apq) > abs_floor && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+            double th = (aqq - app) / (2.0 * apq);
+            double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            s = tt * c;
+            *changed = 1;
+          }
+        }
+        pp[t] = p; pq[t] = q; pc[t] = c; ps[t] = s;
+      }
+      __syncthreads();
+      // rows: A <- R^T A
+      for (int e = t; e < npair * k; e += blockDim.x) {
+        int i = e / k, j = e - i * k;
+        double s = ps[i];
+        if (s == 0.0) continue;
+        double c = pc[i];
+        int p = pp[i], q = pq[i];
+        double ap = A[p * LDA + j], aq = A[q * LDA + j];
+        A[p * LDA + j] = c * ap - s * aq;
+        A[q * LDA + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns: A <- A R, V <- V R
+      for (int e = t; e < npair * k; e += blockDim.x) {
+        int i = e / k, j = e - i * k;
+        double s = ps[i];
+        if (s == 0.0) continue;
+        double c = pc[i];
+        int p = pp[i], q = pq[i];
+        double ap = A[j * LDA + p], aq = A[j * LDA + q];
+        A[j * LDA + p] = c * ap - s * aq;
+        A[j * LDA + q] = s * ap + c * aq;
+        double vp = V[j * LDA + p], vq = V[j * LDA + q];
+        V[j * LDA + p] = c * vp - s * vq;
+        V[j * LDA + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    if (*changed == 0) break;
+    __syncthreads();
+  }
+  __syncthreads();
+}
+
+// Rayleigh-Ritz: SVQB basis of span(S) from G_B, then eigenpairs of the
+// projected G_A (Algorithm 1, RR(S, nev)).
+__global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRArgs a,
+                                            double *Y, double *theta, DevStatus *st) {
+  __shared__ double M1[kMaxW * LDA], M2[kMaxW * LDA], M3[kMaxW * LDA];
+  __shared__ double sc[kMaxW], lam[kMaxW];
+  __shared__ double pc[kMaxW / 2 + 1], ps[kMaxW / 2 + 1];
+  __shared__ int pp[kMaxW / 2 + 1], pq[kMaxW / 2 + 1];
+  __shared__ int kept_idx[kMaxW], perm[kMaxW];
+  __shared__ int nkept, changed;
+  const int t = threadIdx.x;
+  const int w = a.w, m = a.m;
+  const double *GA = gram;
+  const double *GB = gram + kMaxW * kMaxW;
+  int restarted = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const int wl = attempt == 0 ? w : a.p_begin;   // drop P on retry
+    if (t < kMaxW) {
+      double g = (t < wl) ? GB[t * kMaxW + t] : 0.0;
+      sc[t] = (t < wl && g > 0.0) ? 1.0 / sqrt(g) : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < w * w; e += blockDim.x) {
+      int i = e / w, j = e - i * w;
+      int lo = i < j ? i : j, hi = i < j ? j : i;
+      double s = sc[i] * sc[j];
+      M1[i * LDA + j] = GB[lo * kMaxW + hi] * s;
+      M3[i * LDA + j] = GA[lo * kMaxW + hi] * s;
+    }
+    __syncthreads();
+    jacobi_eig(M1, M2, w, pc, ps, pp, pq, &changed);
+    if (t < w) lam[t] = M1[t * LDA + t];
+    __syncthreads();
+    if (t == 0) {
+      double smax = 0.0;
+      for (int j = 0; j < w; ++j) smax = fmax(smax, lam[j]);
+      int q = 0;
+      for (int j = 0; j < w; ++j)
+        if (lam[j] > a.drop_tol * smax && lam[j] > 0.0) kept_idx[q++] = j;
+      nkept = q;
+    }
+    __syncthreads();
+    const int k = nkept;
+    // C = U_kept diag(sigma^-1/2) -> M1 (w x k)
+    for (int e = t; e < w * k; e += blockDim.x) {
+      int i = e / k, q = e - i * k;
+      int j = kept_idx[q];
+      M1[i * LDA + q] = M2[i * LDA + j] / sqrt(lam[j]);
+    }
+    __syncthreads();
+    if (k >= m || attempt == 1 || a.p_begin >= w) {
+      if (k < m) {
+        // breakdown: keep X as it is
+        for (int e = t; e < kMaxW * kMaxNev; e += blockDim.x) {
+          int i = e / kMaxNev, c = e - i * kMaxNev;
+          Y[e] = (i == c && c < m) ? 1.0 : 0.0;
+        }
+        if (t == 0) {
+          st->kept = k;
+          st->restarted = restarted;
+          st->breakdown = 1;
+        }
+        return;
+      }
+      // T1 = As C -> M2 (w x k)
+      for (int e = t; e < w * k; e += blockDim.x) {
+        int i = e / k, q = e - i * k;
+        double s = 0.0;
+        for (int j = 0; j < w; ++j) s += M3[i * LDA + j] * M1[j * LDA + q];
+        M2[i * LDA + q] = s;
+      }
+      __syncthreads();
+      // A' = C^T T1 -> M3 (k x k), symmetrised
+      for (int e = t; e < k * k; e += blockDim.x) {
+        int p = e / k, q = e - p * k;
+        if (p > q) continue;
+        double s1 = 0.0, s2 = 0.0;
+        for (int j = 0; j < w; ++j) {
+          s1 += M1[j * LDA + p] * M2[j * LDA + q];
+          s2 += M1[j * LDA + q] * M2[j * LDA + p];
+        }
+        double v = 0.5 * (s1 + s2);
+        M3[p * LDA + q] = v;
+        M3[q * LDA + p] = v;
+      }
+      __syncthreads();
+      jacobi_eig(M3, M2, k, pc, ps, pp, pq, &changed);
+      if (t < k) lam[t] = M3[t * LDA + t];
+      __syncthreads();
+      if (t < k) {
+        int rank = 0;
+        double v = lam[t];
+        for (int j = 0; j < k; ++j)
+          if (lam[j] < v || (lam[j] == v && j < t)) ++rank;
+        perm[rank] = t;
+      }
+      __syncthreads();
+      // Y = diag(sc) C Z[:, perm[:m]]
+      for (int e = t; e < kMaxW * kMaxNev; e += blockDim.x) {
+        int i = e / kMaxNev, c = e - i * kMaxNev;
+        double s = 0.0;
+        if (i < w && c < m) {
+          int zc = perm[c];
+          for (int q = 0; q < k; ++q) s += M1[i * LDA + q] * M2[q * LDA + zc];
+          s *= sc[i];
+        }
+        Y[e] = s;
+      }
+      if (t < m) theta[t] = lam[perm[t]];
+      if (t == 0) {
+        st->kept = k;
+        st->restarted = restarted;
+        st->breakdown = 0;
+      }
+      return;
+    }
+    restarted = 1;
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------- update
+struct UpdDev {
+  int64_t n;
+  int m;
+  int na;
+  int act[kMaxNev];
+  int use_h, use_p;
+  int offH, offP;     // rows of Y for the H and P parts
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(T *X, const T *__restrict__ H, T *P,
+                                                const T *__restrict__ LH, T *LP,
+                                                const double *__restrict__ Yg, UpdDev a) {
+  __shared__ double sY[kMaxW * kMaxNev];
+  __shared__ double sX[256], sH[256], sP[256], sLH[256], sLP[256];
+  const int m = a.m;
+  const int rc = 256 / m;       // rows per chunk
+  const int t = threadIdx.x;
+  for (int e = t; e < kMaxW * kMaxNev; e += blockDim.x) sY[e] = Yg[e];
+  const int row = t / m;
+  const int c = t - row * m;
+  const bool live = row < rc;
+  const bool write_p = a.use_h || a.use_p;
+  for (int64_t r0 = (int64_t)blockIdx.x * rc; r0 < a.n; r0 += (int64_t)gridDim.x * rc) {
+    const int64_t base = r0 * m;
+    const int64_t lim = min((int64_t)rc, a.n - r0) * m;
+    __syncthreads();
+    if (t < lim) {
+      sX[t] = double(X[base + t]);
+      if (a.use_h) { sH[t] = double(H[base + t]); sLH[t] = double(LH[base + t]); }
+      if (a.use_p) { sP[t] = double(P[base + t]); sLP[t] = double(LP[base + t]); }
+    }
+    __syncthreads();
+    if (live && t < lim) {
+      double p = 0.0, lp = 0.0, x = 0.0;
+      const int o = row * m;
+      if (a.use_h)
+        for (int q = 0; q < a.na; ++q) {
+          double y = sY[(a.offH + q) * kMaxNev + c];
+          p += sH[o + a.act[q]] * y;
+          lp += sLH[o + a.act[q]] * y;
+        }
+      if (a.use_p)
+        for (int q = 0; q < a.na; ++q) {
+          double y = sY[(a.offP + q) * kMaxNev + c];
+          p += sP[o + a.act[q]] * y;
+          lp += sLP[o + a.act[q]] * y;
+        }
+      for (int k = 0; k < m; ++k) x += sX[o + k] * sY[k * kMaxNev + c];
+      x += p;
+      X[base + t] = T(x);
+      if (write_p) {
+        P[base + t] = T(p);
+        LP[base + t] = T(lp);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- finalize
+// Sum partials[b][0..2*kMaxNev) over b in a fixed order -> out.
+__device__ void sum_partials_block(const double *partials, int nblocks, double *out) {
+  __shared__ double s[256];
+  const int t = threadIdx.x;
+  const int q = t / 8, l = t % 8;   // 32 sums x 8 lanes
+  double v = 0.0;
+  for (int b = l; b < nblocks; b += 8) v += partials[(int64_t)b * 2 * kMaxNev + q];
+  s[t] = v;
+  __syncthreads();
+  if (l == 0) {
+    double tot = 0.0;
+    for (int u = 0; u < 8; ++u) tot += s[q * 8 + u];
+    out[q] = tot;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const double *partials, int nblocks,
+                                                  int m, const double *theta, double tol,
+                                                  int locking, DevStatus *st) {
+  __shared__ double sums[2 * kMaxNev];
+  sum_partials_block(partials, nblocks, sums);
+  if (threadIdx.x == 0) {
+    double floor_th = m > 1 ? theta[1] : theta[0];
+    int nconv = 0, na = 0;
+    bool conv[kMaxNev];
+    for (int c = 0; c < m; ++c) {
+      double scale = fmax(theta[c], floor_th);
+      if (!(scale > 0.0)) scale = 1.0;
+      double rn = sqrt(sums[c]), xn = sqrt(sums[kMaxNev + c]);
+      double rho = xn > 0.0 ? rn / (scale * xn) : INFINITY;
+      st->rho[c] = rho;
+      st->theta[c] = theta[c];
+      conv[c] = rho <= tol;
+      nconv += conv[c] ? 1 : 0;
+    }
+    for (int c = 0; c < m; ++c)
+      if (!conv[c] || (!locking && nconv < m)) st->act[na++] = c;
+    st->nact = na;
+    st->nconv = nconv;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double *partials, int nblocks,
+                                                      double *out) {
+  __shared__ double sums[2 * kMaxNev];
+  sum_partials_block(partials, nblocks, sums);
+  if (threadIdx.x < 2 * kMaxNev) out[threadIdx.x] = sums[threadIdx.x];
+}
+
+// Per-column block sums with a fixed lane -> column assignment.
+__device__ void colsum2(int c, double v1, double v2, int m, double *out) {
+  __shared__ double s1[256], s2[256];
+  __shared__ int sc[256];
+  int t = threadIdx.x;
+  s1[t] = v1;
+  s2[t] = v2;
+  sc[t] = c;
+  __syncthreads();
+  if (t < m) {
+    double a = 0.0, b = 0.0;
+    for (int u = 0; u < (int)blockDim.x; ++u)
+      if (sc[u] == t) { a += s1[u]; b += s2[u]; }
+    out[t] = a;
+    out[kMaxNev + t] = b;
+  }
+}
+
+// Rayleigh quotient partials: sum x.lx and sum b x^2 per column.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rq(const T *X, const double *LX, int64_t n, int m,
+                                            const double *bdiag, double *partials) {
+  const int rc = 256 / m;
+  const int row = threadIdx.x / m;
+  const int c = threadIdx.x % m;
+  const bool live = threadIdx.x < rc * m;
+  double a = 0.0, b = 0.0;
+  if (live)
+    for (int64_t r = (int64_t)blockIdx.x * rc + row; r < n; r += (int64_t)gridDim.x * rc) {
+      double x = double(X[r * m + c]);
+      double bd = bdiag ? bdiag[r] : 1.0;
+      a += x * LX[r * m + c];
+      b += bd * x * x;
+    }
+  colsum2(live ? c : -1, a, b, m, partials + (int64_t)blockIdx.x * 2 * kMaxNev);
+}
+
+// Residual partials: sum (lx - theta b x)^2 / b and sum b x^2 per column.
+template <typename T>
+__global__ __launch_bounds__(256) void k_res(const T *X, const double *LX, int64_t n, int m,
+                                             const double *bdiag, const double *theta,
+                                             double *partials) {
+  const int rc = 256 / m;
+  const int row = threadIdx.x / m;
+  const int c = threadIdx.x % m;
+  const bool live = threadIdx.x < rc * m;
+  double a = 0.0, b = 0.0;
+  if (live) {
+    double th = theta[c];
+    for (int64_t r = (int64_t)blockIdx.x * rc + row; r < n; r += (int64_t)gridDim.x * rc) {
+      double x = double(X[r * m + c]);
+      double bd = bdiag ? bdiag[r] : 1.0;
+      double res = LX[r * m + c] - th * bd * x;
+      a += res * res / bd;
+      b += bd * x * x;
+    }
+  }
+  colsum2(live ? c : -1, a, b, m, partials + (int64_t)blockIdx.x * 2 * kMaxNev);
+}
+
+// Column argmax |x| (lowest index on ties): block partials (value, index).
+template <typename T>
+__global__ __launch_bounds__(256) void k_colmax(const T *X, int64_t n, int m, double *pv,
+                                                int64_t *pi) {
+  const int rc = 256 / m;
+  const int row = threadIdx.x / m;
+  const int c = threadIdx.x % m;
+  const bool live = threadIdx.x < rc * m;
+  double bv = -1.0;
+  int64_t bi = INT64_MAX;
+  if (live)
+    for (int64_t r = (int64_t)blockIdx.x * rc + row; r < n; r += (int64_t)gridDim.x * rc) {
+      double v = fabs(double(X[r * m + c]));
+      if (v > bv || (v == bv && r < bi)) { bv = v; bi = r; }
+    }
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  __shared__ int scol[256];
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  scol[threadIdx.x] = live ? c : -1;
+  __syncthreads();
+  if (threadIdx.x < m) {
+    double v = -1.0;
+    int64_t ix = INT64_MAX;
+    for (int u = 0; u < (int)blockDim.x; ++u)
+      if (scol[u] == (int)threadIdx.x)
+        if (sv[u] > v || (sv[u] == v && si[u] < ix)) { v = sv[u]; ix = si[u]; }
+    pv[blockIdx.x * kMaxNev + threadIdx.x] = v;
+    pi[blockIdx.x * kMaxNev + threadIdx.x] = ix;
+  }
+}
+
+template <typename T>
+__global__ void k_colsign(const T *X, int m, int nblocks, const double *pv,
+                          const int64_t *pi, double *sign) {
+  int c = threadIdx.x;
+  if (c >= m) return;
+  double v = -1.0;
+  int64_t ix = INT64_MAX;
+  for (int b = 0; b < nblocks; ++b) {
+    double bv = pv[b * kMaxNev + c];
+    int64_t bi = pi[b * kMaxNev + c];
+    if (bv > v || (bv == v && bi < ix)) { v = bv; ix = bi; }
+  }
+  double x = (ix == INT64_MAX) ? 1.0 : double(X[ix * m + c]);
+  sign[c] = x < 0 ? -1.0 : 1.0;
+}
+
+struct Scales { double s[kMaxNev]; };
+
+template <typename T>
+__global__ void k_colscale(T *X, int64_t n, int m, const double *sign, Scales sc) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int c = (int)(e % m);
+    X[e] = T(double(X[e]) * sign[c] * sc.s[c]);
+  }
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin *in, Tout *out, int64_t count) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = Tout(in[e]);
+}
+
+template <typename T>
+__global__ void k_copy_cols(const T *in, int ldin, T *out, int ldout, int64_t n, int m) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = e / m;
+    int c = (int)(e - i * m);
+    out[i * ldout + c] = in[i * ldin + c];
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+template <typename T>
+void launch_init_random(T *X, int64_t n, int m, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL((k_init_random<T>), dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s,
+                     X, n * m, seed);
+}
+template <typename T>
+void launch_init_piecewise(T *X, int64_t n, int m, hipStream_t s) {
+  hipLaunchKernelGGL((k_init_piecewise<T>), dim3(grid_for(n * m, 256, 4096)), dim3(256), 0,
+                     s, X, n, m);
+}
+
+size_t gram_partial_doubles(int max_blocks) {
+  return (size_t)max_blocks * 2 * kMaxW * kMaxW;
+}
+
+template <typename T>
+int gram(const T *X, const T *LX, const T *H, const T *LH, const T *P, const T *LP,
+         const GramArgs &a, double *partials, int max_blocks, double *gram_out,
+         hipStream_t s) {
+  GramDev d;
+  d.n = a.n;
+  d.m = a.m;
+  int na = a.act.count;
+  d.use_h = a.use_h && na > 0;
+  d.use_p = a.use_p && na > 0;
+  d.offH = a.m;
+  d.offP = a.m + (d.use_h ? na : 0);
+  d.w = a.m + (d.use_h ? na : 0) + (d.use_p ? na : 0);
+  for (int c = 0; c < kMaxNev; ++c) d.inv[c] = -1;
+  for (int q = 0; q < na; ++q) d.inv[a.act.col[q]] = q;
+  d.bdiag = a.bdiag;
+  int NT = (d.w + 15) / 16;
+  int64_t rows_per_block = ceil_div(a.n, max_blocks);
+  rows_per_block = ceil_div(rows_per_block, kCh) * kCh;
+  int nb = (int)ceil_div(a.n, rows_per_block);
+  if (nb < 1) nb = 1;
+  switch (NT) {
+    case 1:
+      hipLaunchKernelGGL((k_gram<T, 1>), dim3(nb), dim3(256), 0, s, d, X, LX, H, LH, P, LP,
+                         rows_per_block, partials);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_gram<T, 2>), dim3(nb), dim3(256), 0, s, d, X, LX, H, LH, P, LP,
+                         rows_per_block, partials);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_gram<T, 3>), dim3(nb), dim3(256), 0, s, d, X, LX, H, LH, P, LP,
+                         rows_per_block, partials);
+      break;
+    default:
+      return SPHX_E_INVALID_ARG;
+  }
+  int W = 16 * NT;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(grid_for(2 * W * W, 256, 64)), dim3(256), 0, s,
+                     (const double *)partials, nb, NT, gram_out);
+  return hipGetLastError() == hipSuccess ? SPHX_OK : SPHX_E_HIP;
+}
+
+void launch_rr(const double *gram_out, const RRArgs &a, double *Y, double *theta,
+               DevStatus *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_rr, dim3(1), dim3(256), 0, s, gram_out, a, Y, theta, st);
+}
+
+template <typename T>
+void launch_update(T *X, const T *H, T *P, const T *LH, T *LP, const double *Y,
+                   const UpdateArgs &a, hipStream_t s) {
+  UpdDev d;
+  d.n = a.n;
+  d.m = a.m;
+  d.na = a.act.count;
+  for (int q = 0; q < kMaxNev; ++q) d.act[q] = q < d.na ? a.act.col[q] : 0;
+  d.use_h = a.use_h && d.na > 0;
+  d.use_p = a.use_p && d.na > 0;
+  d.offH = a.m;
+  d.offP = a.m + (d.use_h ? d.na : 0);
+  int rc = 256 / a.m;
+  hipLaunchKernelGGL((k_update<T>), dim3(grid_for(a.n, rc, 8192)), dim3(256), 0, s, X, H, P,
+                     LH, LP, Y, d);
+}
+
+void launch_finalize(const double *norm_partials, int n_blocks, int m, const double *theta,
+                     double tol, int locking, DevStatus *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, norm_partials, n_blocks, m, theta,
+                     tol, locking, st);
+}
+
+template <typename T>
+void launch_rq_partials(const T *X, const double *LX, int64_t n, int m, const double *bdiag,
+                        double *partials, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_rq<T>), dim3(nblocks), dim3(256), 0, s, X, LX, n, m, bdiag, partials);
+}
+template <typename T>
+void launch_res_partials(const T *X, const double *LX, int64_t n, int m, const double *bdiag,
+                         const double *theta, double *partials, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_res<T>), dim3(nblocks), dim3(256), 0, s, X, LX, n, m, bdiag, theta,
+                     partials);
+}
+void launch_sum_partials(const double *partials, int nblocks, int cols, double *out,
+                         hipStream_t s) {
+  (void)cols;
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, nblocks, out);
+}
+
+constexpr int kColBlocks = 256;
+size_t normalize_scratch_bytes() {
+  return (size_t)kColBlocks * kMaxNev * (sizeof(double) + sizeof(int64_t)) + 256 * 8;
+}
+
+template <typename T>
+int normalize_columns(T *X, int64_t n, int m, const double *scale_host, void *scratch,
+                      hipStream_t s) {
+  double *pv = static_cast<double *>(scratch);
+  int64_t *pi = reinterpret_cast<int64_t *>(pv + kColBlocks * kMaxNev);
+  double *sign = reinterpret_cast<double *>(pi + kColBlocks * kMaxNev);
+  int nb = (int)grid_for(n, 256 / m, kColBlocks);
+  hipLaunchKernelGGL((k_colmax<T>), dim3(nb), dim3(256), 0, s, X, n, m, pv, pi);
+  hipLaunchKernelGGL((k_colsign<T>), dim3(1), dim3(64), 0, s, X, m, nb, pv, pi, sign);
+  Scales sc;
+  for (int c = 0; c < kMaxNev; ++c) sc.s[c] = c < m ? scale_host[c] : 1.0;
+  hipLaunchKernelGGL((k_colscale<T>), dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s, X, n,
+                     m, (const double *)sign, sc);
+  return hipGetLastError() == hipSuccess ? SPHX_OK : SPHX_E_HIP;
+}
+
+template <typename Tin, typename Tout>
+void launch_convert(const Tin *in, Tout *out, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(grid_for(count, 256, 4096)), dim3(256), 0, s,
+                     in, out, count);
+}
+template <typename T>
+void launch_copy_cols(const T *in, int ldin, T *out, int ldout, int64_t n, int m,
+                      hipStream_t s) {
+  hipLaunchKernelGGL((k_copy_cols<T>), dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s, in,
+                     ldin, out, ldout, n, m);
+}
+
+#define SPHX_INST(T)                                                                        \
+  template void launch_init_random<T>(T *, int64_t, int, uint64_t, hipStream_t);           \
+  template void launch_init_piecewise<T>(T *, int64_t, int, hipStream_t);                  \
+  template int gram<T>(const T *, const T *, const T *, const T *, const T *, const T *,   \
+                       const GramArgs &, double *, int, double *, hipStream_t);            \
+  template void launch_update<T>(T *, const T *, T *, const T *, T *, const double *,      \
+                                 const UpdateArgs &, hipStream_t);                         \
+  template void launch_rq_partials<T>(const T *, const double *, int64_t, int,             \
+                                      const double *, double *, int, hipStream_t);         \
+  template void launch_res_partials<T>(const T *, const double *, int64_t, int,            \
+                                       const double *, const double *, double *, int,      \
+                                       hipStream_t);                                       \
+  template int normalize_columns<T>(T *, int64_t, int, const double *, void *, hipStream_t); \
+  template void launch_copy_cols<T>(const T *, int, T *, int, int64_t, int, hipStream_t);
+SPHX_INST(float)
+SPHX_INST(double)
+#undef SPHX_INST
+template void launch_convert<float, double>(const float *, double *, int64_t, hipStream_t);
+template void launch_convert<double, float>(const double *, float *, int64_t, hipStream_t);
+template void launch_convert<double, double>(const double *, double *, int64_t, hipStream_t);
+template void launch_convert<float, float>(const float *, float *, int64_t, hipStream_t);
+
+}  // namespace sphx

@@ -1,0 +1,182 @@
+// Host-side launch interfaces of the HIP kernels.
+#pragma once
+
+#include "common.h"
+
+namespace sphx {
+
+// ------------------------------------------------------------------ setup
+// Row bins for the Laplacian product: rows with at most kShortDeg neighbours
+// are processed by a lane group each, rows up to kHubDeg by a wavefront
+// each, longer rows in kHubChunk-entry chunks by one wavefront per chunk.
+constexpr int kShortDeg = 32;
+constexpr int kHubDeg = 16384;
+constexpr int kHubChunk = 4096;
+
+struct SpmmPlan {
+  bool binned = false;          // false: every row is short, natural order
+  const int32_t *short_rows = nullptr;
+  int64_t n_short = 0;
+  const int32_t *mid_rows = nullptr;
+  int64_t n_mid = 0;
+  const int32_t *hub_rows = nullptr;     // hub rows
+  int64_t n_hub = 0;
+  const int64_t *chunk_k0 = nullptr;     // per chunk: first entry
+  const int64_t *chunk_k1 = nullptr;     // per chunk: one past last entry
+  const int32_t *hub_chunk_begin = nullptr;  // per hub: first chunk (n_hub+1)
+  int64_t n_chunks = 0;
+  double *hub_partial = nullptr;         // n_chunks * kMaxNev scratch (T-sized)
+};
+
+// Degree statistics of a graph (pattern and weighted).
+struct DegreeStats {
+  int64_t max_deg, sum_deg, min_deg;
+  double max_wdeg, min_wdeg;
+};
+
+int validate_graph(sphx_graph *g, hipStream_t s, int32_t *flags_dev, int *flags_host);
+// d64[i] = weighted degree; dT (float or double copy, may be null);
+// returns statistics through a device buffer then host.
+int compute_degrees(sphx_graph *g, double *d64, float *d32, void *scratch,
+                    DegreeStats *out, void *pinned, hipStream_t s);
+int build_plan(sphx_graph *g, Arena &ws, SpmmPlan *plan, const DegreeStats &st,
+               void *pinned, hipStream_t s);
+size_t plan_bytes(sphx_graph *g);
+
+// ------------------------------------------------------------------ spmm
+// Epilogue parameters.
+template <typename T>
+struct EpiStoreP { T *Y; int ldy; };
+template <typename T>
+struct EpiResidualP {
+  T *LX;             // L x output (ld)
+  T *OUT;            // residual (or Jacobi-preconditioned residual) output
+  int ld;
+  const double *theta;   // device, per column
+  const double *d64;     // weighted degrees
+  int generalized;
+  int jacobi;
+};
+template <typename T>
+struct EpiChebP {
+  const T *prev;       // previous iterate is prev_scale * prev (nullable = 0)
+  const T *R;          // right-hand side
+  T *OUT;
+  int ld;
+  double src_scale;    // the gathered source is src_scale * X
+  double prev_scale;
+  double alpha, beta;
+  const double *dinv;  // nullable: 1
+};
+
+// Norm partials: up to kMaxNormBlocks blocks of 2*kMaxNev doubles.
+constexpr int kMaxNormBlocks = 4096;
+
+template <typename T>
+int spmm_store(sphx_graph *g, const SpmmPlan &plan, const T *X, int ldx,
+               const ColMap &cm, EpiStoreP<T> epi, hipStream_t s);
+template <typename T>
+int spmm_residual(sphx_graph *g, const SpmmPlan &plan, const T *X, int ldx,
+                  const ColMap &cm, EpiResidualP<T> epi, double *norm_partials,
+                  int *n_norm_blocks, hipStream_t s);
+template <typename T>
+int spmm_cheb(sphx_graph *g, const SpmmPlan &plan, const T *X, int ldx,
+              const ColMap &cm, EpiChebP<T> epi, hipStream_t s);
+
+// ------------------------------------------------------------------ dense
+template <typename T>
+void launch_init_random(T *X, int64_t n, int m, uint64_t seed, hipStream_t s);
+template <typename T>
+void launch_init_piecewise(T *X, int64_t n, int m, hipStream_t s);
+
+// Gram matrices of S = [X(all m), H(act), P(act, if have_p)] against
+// LS = [LX, LH, LP] and B S.  Output: reduced upper-tile entries in
+// gram_out[2][kMaxW][kMaxW] (A then B), row-major, only i <= j meaningful.
+struct GramArgs {
+  int64_t n;
+  int m;               // X width (= ld of every block)
+  ColMap act;          // active columns for H and P
+  int use_h, use_p;
+  const double *bdiag; // nullable: B = I
+};
+template <typename T>
+int gram(const T *X, const T *LX, const T *H, const T *LH, const T *P,
+         const T *LP, const GramArgs &a, double *partials, int max_blocks,
+         double *gram_out, hipStream_t s);
+size_t gram_partial_doubles(int max_blocks);
+constexpr int kGramBlocks = 512;
+
+// Rayleigh-Ritz on the reduced Gram matrices (one workgroup, FP64).
+// Writes Y (kMaxW x kMaxNev, row-major: Y[k * kMaxNev + c]) and theta
+// into `rr_out`, and kept / restarted / breakdown into the status.
+struct RRArgs {
+  int m;            // nev
+  int w;            // total basis width
+  int p_begin;      // first P column in the basis (== w if no P)
+  double drop_tol;
+};
+void launch_rr(const double *gram_out, const RRArgs &a, double *Y, double *theta,
+               DevStatus *st, hipStream_t s);
+
+// X <- [X, H_a, P_a] Y ; P <- [0, H_a, P_a] Y ; LP <- [0, LH_a, LP_a] Y
+struct UpdateArgs {
+  int64_t n;
+  int m;
+  ColMap act;
+  int use_h, use_p;
+};
+template <typename T>
+void launch_update(T *X, const T *H, T *P, const T *LH, T *LP, const double *Y,
+                   const UpdateArgs &a, hipStream_t s);
+
+// Reduce norm partials -> rho, convergence, active list (one workgroup).
+void launch_finalize(const double *norm_partials, int n_blocks, int m,
+                     const double *theta, double tol, int locking,
+                     DevStatus *st, hipStream_t s);
+
+// Rayleigh quotients / residual norms in FP64 of a final block.
+template <typename T>
+void launch_rq_partials(const T *X, const double *LX, int64_t n, int m,
+                        const double *bdiag, double *partials, int nblocks,
+                        hipStream_t s);
+template <typename T>
+void launch_res_partials(const T *X, const double *LX, int64_t n, int m,
+                         const double *bdiag, const double *theta,
+                         double *partials, int nblocks, hipStream_t s);
+// Sum partials[nblocks][2*kMaxNev] into out[2*kMaxNev] (fixed order).
+void launch_sum_partials(const double *partials, int nblocks, int cols,
+                         double *out, hipStream_t s);
+// Per-column argmax |x| (lowest index on ties) -> sign; scale columns.
+template <typename T>
+int normalize_columns(T *X, int64_t n, int m, const double *scale_dev,
+                      void *scratch, hipStream_t s);
+size_t normalize_scratch_bytes();
+
+template <typename Tin, typename Tout>
+void launch_convert(const Tin *in, Tout *out, int64_t count, hipStream_t s);
+template <typename T>
+void launch_copy_cols(const T *in, int ldin, T *out, int ldout, int64_t n,
+                      int m, hipStream_t s);
+
+// ------------------------------------------------------------------ split
+size_t split_scratch_bytes(int64_t n, int K);
+template <typename T>
+int split_pow2(sphx_graph *g, const T *coords, int ld, int ncoord, int K,
+               int32_t *part, void *scratch, void *pinned, hipStream_t s,
+               std::string *err);
+
+// ---------------------------------------------------------------- quality
+size_t quality_scratch_bytes(int K);
+int quality(sphx_graph *g, const int32_t *part, int K, double *cut,
+            double *imbalance, int64_t *part_weights, void *scratch,
+            void *pinned, hipStream_t s, std::string *err);
+
+// ---------------------------------------------------------------- adjoint
+size_t adjoint_scratch_bytes(int64_t n, int nev);
+int eig_backward(sphx_graph *g, const SpmmPlan &plan, int problem, int nev,
+                 const double *eigvals, const double *V, const double *g_vals,
+                 const double *gV, double cg_tol, int cg_max_iter,
+                 const double *d64, double *grad, void *scratch, void *pinned,
+                 hipStream_t s, std::string *err);
+
+}  // namespace sphx

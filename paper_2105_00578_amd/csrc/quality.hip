@@ -1,0 +1,149 @@
+// Partition quality (Sec. 3.1): cutsize of Eq. 1, part weights W_k and the
+// imbalance max_k W_k / W_avg.
+//
+// Exactness: unit weights are counted in int64.  Float edge weights are
+// summed exactly in 128-bit fixed point: with e0 the exponent of the last
+// mantissa bit of the smallest weight, every weight is an integer multiple of
+// 2^e0, so the cut is an exact integer times 2^e0, rounded once at the end.
+#include <cmath>
+
+#include "fixed.h"
+#include "kernels.h"
+
+namespace sphx {
+namespace {
+
+// one wavefront per row; each lane accumulates its own exact partial
+template <typename IdxT, typename WT>
+__global__ __launch_bounds__(256) void k_cut(int64_t n, const IdxT *rp, const int32_t *col,
+                                             const WT *w, const int32_t *part, int e0,
+                                             unsigned long long *out) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x / 64;
+  U128 acc{0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * wpb + threadIdx.x / 64; i < n;
+       i += (int64_t)gridDim.x * wpb) {
+    int pi = part[i];
+    for (int64_t k = (int64_t)rp[i] + lane; k < (int64_t)rp[i + 1]; k += 64) {
+      int64_t j = col[k];
+      if (j <= i || part[j] == pi) continue;
+      if constexpr (std::is_same_v<WT, Unit>) add128(acc, 1ull, 0ull);
+      else {
+        unsigned long long lo, hi;
+        fixed_of(w[k], e0, lo, hi);
+        add128(acc, lo, hi);
+      }
+    }
+  }
+  __shared__ unsigned long long slo[256], shi[256];
+  slo[threadIdx.x] = acc.lo;
+  shi[threadIdx.x] = acc.hi;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    U128 t{0, 0};
+    for (int u = 0; u < (int)blockDim.x; ++u) add128(t, slo[u], shi[u]);
+    out[2 * blockIdx.x] = t.lo;
+    out[2 * blockIdx.x + 1] = t.hi;
+  }
+}
+
+__global__ void k_part_weights(int64_t n, const int32_t *part, const int32_t *vwgt, int K,
+                               unsigned long long *pw, int *bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int p = part[i];
+    if (p < 0 || p >= K) { atomicOr(bad, 1); continue; }
+    atomicAdd(&pw[p], (unsigned long long)(vwgt ? vwgt[i] : 1));
+  }
+}
+
+constexpr int kCutBlocks = 1024;
+
+double u128_to_double(unsigned __int128 v) {
+  if (v == 0) return 0.0;
+  int nb = 0;
+  for (unsigned __int128 t = v; t; t >>= 1) ++nb;
+  if (nb <= 53) return (double)(unsigned long long)v;
+  int sh = nb - 53;
+  unsigned __int128 top = v >> sh;
+  unsigned __int128 rem = v - (top << sh);
+  unsigned __int128 half = (unsigned __int128)1 << (sh - 1);
+  if (rem > half || (rem == half && (top & 1))) top += 1;   // nearest, ties to even
+  return std::ldexp((double)(unsigned long long)top, sh);
+}
+
+}  // namespace
+
+size_t quality_scratch_bytes(int K) {
+  return align_up(sizeof(unsigned long long) * 2 * kCutBlocks, 256) +
+         align_up(sizeof(unsigned long long) * (size_t)(K > 0 ? K : 1), 256) + 1024;
+}
+
+int quality(sphx_graph *g, const int32_t *part, int K, double *cut, double *imbalance,
+            int64_t *part_weights, void *scratch, void *pinned, hipStream_t s,
+            std::string *err) {
+  Arena a;
+  a.base = static_cast<char *>(scratch);
+  unsigned long long *cp = a.take<unsigned long long>(2 * kCutBlocks);
+  unsigned long long *pw = a.take<unsigned long long>(K);
+  int *bad = a.take<int>(4);
+  // the weight range (and its e0) is known from the degree pass
+  int e0 = 0;
+  if (g->wdt == SPHX_F32) e0 = fixed_exponent<float>(g->wmin);
+  if (g->wdt == SPHX_F64) e0 = fixed_exponent<double>(g->wmin);
+  hipMemsetAsync(pw, 0, sizeof(unsigned long long) * K, s);
+  hipMemsetAsync(bad, 0, sizeof(int) * 4, s);
+  hipLaunchKernelGGL(k_part_weights, dim3(grid_for(g->n, 256, 2048)), dim3(256), 0, s, g->n,
+                     part, g->vwgt, K, pw, bad);
+  unsigned nb = grid_for(g->n, 4, kCutBlocks);
+  auto go = [&](auto it, auto wt) {
+    using IdxT = decltype(it);
+    using WT = decltype(wt);
+    hipLaunchKernelGGL((k_cut<IdxT, WT>), dim3(nb), dim3(256), 0, s, g->n,
+                       (const IdxT *)g->rowptr, g->col, (const WT *)g->w, part, e0, cp);
+  };
+  if (g->rp64) {
+    if (g->wdt == SPHX_UNIT) go(int64_t{}, Unit{});
+    else if (g->wdt == SPHX_F32) go(int64_t{}, float{});
+    else go(int64_t{}, double{});
+  } else {
+    if (g->wdt == SPHX_UNIT) go(int32_t{}, Unit{});
+    else if (g->wdt == SPHX_F32) go(int32_t{}, float{});
+    else go(int32_t{}, double{});
+  }
+  if (hipGetLastError() != hipSuccess) {
+    *err = "quality kernel launch failed";
+    return SPHX_E_HIP;
+  }
+  std::vector<unsigned long long> hc(2 * nb), hw(K);
+  int hbad = 0;
+  if (hipMemcpyAsync(hc.data(), cp, sizeof(unsigned long long) * 2 * nb,
+                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(hw.data(), pw, sizeof(unsigned long long) * K, hipMemcpyDeviceToHost,
+                     s) != hipSuccess ||
+      hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    *err = "quality: copy failed";
+    return SPHX_E_HIP;
+  }
+  if (hbad) {
+    *err = "part id out of range [0, K)";
+    return SPHX_E_INVALID_ARG;
+  }
+  unsigned __int128 tot = 0;
+  for (unsigned b = 0; b < nb; ++b)
+    tot += ((unsigned __int128)hc[2 * b + 1] << 64) + hc[2 * b];
+  double c = u128_to_double(tot);
+  if (g->wdt != SPHX_UNIT) c = std::ldexp(c, e0);
+  if (cut) *cut = c;
+  unsigned long long mx = 0, sum = 0;
+  for (int k = 0; k < K; ++k) {
+    mx = std::max(mx, hw[k]);
+    sum += hw[k];
+    if (part_weights) part_weights[k] = (int64_t)hw[k];
+  }
+  if (imbalance) *imbalance = sum ? (double)(mx * (unsigned long long)K) / (double)sum : 1.0;
+  return SPHX_OK;
+}
+
+}  // namespace sphx

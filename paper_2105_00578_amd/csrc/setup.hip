@@ -1,0 +1,439 @@
+// Graph validation, degrees and the degree-binned row plan of the Laplacian
+// product.  Degrees are the diagonal of L_C (Eq. 2, weighted); the regular /
+// irregular classification is max degree / average degree <= 10 (Sec. 6.1).
+#include <algorithm>
+
+#include "fixed.h"
+#include "kernels.h"
+
+namespace sphx {
+namespace {
+
+enum : int {
+  F_BAD_GRAPH = 1,
+  F_SELF_LOOP = 2,
+  F_NOT_SYM = 4,
+  F_BAD_WEIGHT = 8,
+};
+
+// One wavefront per row; lanes stride over the row's entries.
+template <typename IdxT, typename WT>
+__global__ __launch_bounds__(256) void k_validate(int64_t n, int64_t nnz,
+                                                  const IdxT *rp, const int32_t *col,
+                                                  const WT *w, const int32_t *vwgt,
+                                                  int *flags) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x / 64;
+  int f = 0;
+  for (int64_t i = (int64_t)blockIdx.x * wpb + threadIdx.x / 64; i < n;
+       i += (int64_t)gridDim.x * wpb) {
+    int64_t b = rp[i], e = rp[i + 1];
+    if (lane == 0) {
+      if (e < b || b < 0 || e > nnz) f |= F_BAD_GRAPH;
+      if (i == 0 && b != 0) f |= F_BAD_GRAPH;
+      if (i == n - 1 && e != nnz) f |= F_BAD_GRAPH;
+      if (vwgt && vwgt[i] < 1) f |= F_BAD_WEIGHT;
+    }
+    if (e < b || b < 0 || e > nnz) continue;
+    for (int64_t k = b + lane; k < e; k += 64) {
+      int64_t j = col[k];
+      if (j < 0 || j >= n) { f |= F_BAD_GRAPH; continue; }
+      if (j == i) f |= F_SELF_LOOP;
+      if (k > b && col[k - 1] >= col[k]) f |= F_BAD_GRAPH;
+      if constexpr (!std::is_same_v<WT, Unit>) {
+        WT wk = w[k];
+        if (!(wk > WT(0)) || !(wk < WT(INFINITY))) f |= F_BAD_WEIGHT;
+      }
+      // symmetric partner (i in row j), binary search
+      int64_t lo = rp[j], hi = rp[j + 1] - 1;
+      bool found = false;
+      int64_t kk = -1;
+      while (lo <= hi) {
+        int64_t mid = (lo + hi) >> 1;
+        int64_t cm = col[mid];
+        if (cm == i) { found = true; kk = mid; break; }
+        if (cm < i) lo = mid + 1; else hi = mid - 1;
+      }
+      if (!found) f |= F_NOT_SYM;
+      else if constexpr (!std::is_same_v<WT, Unit>) {
+        if (!(w[kk] == w[k])) f |= F_NOT_SYM;
+      }
+    }
+  }
+  if (f) atomicOr(flags, f);
+}
+
+// Degrees: one wavefront per row.  The weighted degree is the exact sum of
+// the row's weights rounded once to FP64 (128-bit fixed point, see fixed.h),
+// so it does not depend on any summation order.  Block statistics ->
+// stats[block][4]: max pattern deg, min pattern deg, max wdeg, min wdeg.
+template <typename IdxT, typename WT>
+__global__ __launch_bounds__(256) void k_degrees(int64_t n, const IdxT *rp,
+                                                 const WT *w, int e0, double *d64,
+                                                 float *d32, double *stats) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x / 64;
+  double mx = 0.0, mn = 1e300, wmx = 0.0, wmn = 1e300;
+  for (int64_t i = (int64_t)blockIdx.x * wpb + threadIdx.x / 64; i < n;
+       i += (int64_t)gridDim.x * wpb) {
+    int64_t b = rp[i], e = rp[i + 1];
+    double s = 0.0;
+    if constexpr (std::is_same_v<WT, Unit>) {
+      s = double(e - b);
+    } else {
+      U128 acc{0, 0};
+      for (int64_t k = b + lane; k < e; k += 64) {
+        unsigned long long lo, hi;
+        fixed_of(w[k], e0, lo, hi);
+        add128(acc, lo, hi);
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        unsigned long long lo = __shfl_xor(acc.lo, off);
+        unsigned long long hi = __shfl_xor(acc.hi, off);
+        add128(acc, lo, hi);
+      }
+      s = fixed_to_double(acc, e0);
+    }
+    if (lane == 0) {
+      d64[i] = s;
+      if (d32) d32[i] = float(s);
+      double deg = double(e - b);
+      mx = fmax(mx, deg);
+      mn = fmin(mn, deg);
+      wmx = fmax(wmx, s);
+      wmn = fmin(wmn, s);
+    }
+  }
+  __shared__ double sh[4][256];
+  sh[0][threadIdx.x] = mx;
+  sh[1][threadIdx.x] = mn;
+  sh[2][threadIdx.x] = wmx;
+  sh[3][threadIdx.x] = wmn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int t = 1; t < (int)blockDim.x; ++t) {
+      mx = fmax(mx, sh[0][t]);
+      mn = fmin(mn, sh[1][t]);
+      wmx = fmax(wmx, sh[2][t]);
+      wmn = fmin(wmn, sh[3][t]);
+    }
+    stats[blockIdx.x * 4 + 0] = mx;
+    stats[blockIdx.x * 4 + 1] = mn;
+    stats[blockIdx.x * 4 + 2] = wmx;
+    stats[blockIdx.x * 4 + 3] = wmn;
+  }
+}
+
+// edge-weight range (for the exact cut), block partials
+template <typename WT>
+__global__ __launch_bounds__(256) void k_wrange(int64_t nnz, const WT *w, double *stats) {
+  double mx = 0.0, mn = 1e300;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double v = double(w[k]);
+    mx = fmax(mx, v);
+    mn = fmin(mn, v);
+  }
+  __shared__ double s0[256], s1[256];
+  s0[threadIdx.x] = mx;
+  s1[threadIdx.x] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int t = 1; t < (int)blockDim.x; ++t) {
+      mx = fmax(mx, s0[t]);
+      mn = fmin(mn, s1[t]);
+    }
+    stats[blockIdx.x * 2] = mx;
+    stats[blockIdx.x * 2 + 1] = mn;
+  }
+}
+
+// Deterministic three-way row binning: class 0 short, 1 mid, 2 hub.
+constexpr int kBinRows = 1024;   // rows per block
+
+template <typename IdxT>
+__device__ __forceinline__ int row_class(const IdxT *rp, int64_t i) {
+  int64_t d = rp[i + 1] - rp[i];
+  return d <= kShortDeg ? 0 : (d <= kHubDeg ? 1 : 2);
+}
+
+template <typename IdxT>
+__global__ __launch_bounds__(256) void k_bin_count(int64_t n, const IdxT *rp, int *counts) {
+  __shared__ int c[3];
+  if (threadIdx.x < 3) c[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t r0 = (int64_t)blockIdx.x * kBinRows;
+  for (int t = threadIdx.x; t < kBinRows; t += blockDim.x) {
+    int64_t i = r0 + t;
+    if (i < n) atomicAdd(&c[row_class(rp, i)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) counts[blockIdx.x * 3 + threadIdx.x] = c[threadIdx.x];
+}
+
+__global__ void k_bin_scan(int nblocks, int *counts, int *totals) {
+  // single thread; nblocks <= n/1024
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int acc[3] = {0, 0, 0};
+    for (int b = 0; b < nblocks; ++b)
+      for (int c = 0; c < 3; ++c) {
+        int v = counts[b * 3 + c];
+        counts[b * 3 + c] = acc[c];
+        acc[c] += v;
+      }
+    totals[0] = acc[0];
+    totals[1] = acc[1];
+    totals[2] = acc[2];
+  }
+}
+
+template <typename IdxT>
+__global__ __launch_bounds__(256) void k_bin_scatter(int64_t n, const IdxT *rp,
+                                                     const int *offsets, int32_t *l0,
+                                                     int32_t *l1, int32_t *l2) {
+  // each thread owns kBinRows/256 consecutive rows; ranks via a block scan
+  __shared__ int cnt[3][256];
+  const int per = kBinRows / 256;
+  int64_t r0 = (int64_t)blockIdx.x * kBinRows + (int64_t)threadIdx.x * per;
+  int local[3] = {0, 0, 0};
+  for (int t = 0; t < per; ++t) {
+    int64_t i = r0 + t;
+    if (i < n) local[row_class(rp, i)]++;
+  }
+  for (int c = 0; c < 3; ++c) cnt[c][threadIdx.x] = local[c];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    int c = threadIdx.x, acc = 0;
+    for (int t = 0; t < 256; ++t) {
+      int v = cnt[c][t];
+      cnt[c][t] = acc;
+      acc += v;
+    }
+  }
+  __syncthreads();
+  int pos[3];
+  for (int c = 0; c < 3; ++c) pos[c] = offsets[blockIdx.x * 3 + c] + cnt[c][threadIdx.x];
+  int32_t *lists[3] = {l0, l1, l2};
+  for (int t = 0; t < per; ++t) {
+    int64_t i = r0 + t;
+    if (i < n) {
+      int c = row_class(rp, i);
+      lists[c][pos[c]++] = (int32_t)i;
+    }
+  }
+}
+
+template <typename F>
+void with_types(sphx_graph *g, F &&f) {
+  if (g->rp64) {
+    if (g->wdt == SPHX_UNIT) f(int64_t{}, Unit{});
+    else if (g->wdt == SPHX_F32) f(int64_t{}, float{});
+    else f(int64_t{}, double{});
+  } else {
+    if (g->wdt == SPHX_UNIT) f(int32_t{}, Unit{});
+    else if (g->wdt == SPHX_F32) f(int32_t{}, float{});
+    else f(int32_t{}, double{});
+  }
+}
+
+}  // namespace
+
+int validate_graph(sphx_graph *g, hipStream_t s, int32_t *flags_dev, int *flags_host) {
+  SPHX_HIP(g->h, hipMemsetAsync(flags_dev, 0, sizeof(int), s));
+  unsigned gb = grid_for(g->n, 4, 1 << 16);
+  with_types(g, [&](auto it, auto wt) {
+    using IdxT = decltype(it);
+    using WT = decltype(wt);
+    hipLaunchKernelGGL((k_validate<IdxT, WT>), dim3(gb), dim3(256), 0, s, g->n, g->nnz,
+                       (const IdxT *)g->rowptr, g->col, (const WT *)g->w, g->vwgt,
+                       (int *)flags_dev);
+  });
+  SPHX_HIP(g->h, hipGetLastError());
+  SPHX_HIP(g->h, hipMemcpyAsync(flags_host, flags_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+  SPHX_HIP(g->h, hipStreamSynchronize(s));
+  int f = *flags_host;
+  if (f & F_BAD_GRAPH) return set_err(g->h, SPHX_E_BAD_GRAPH,
+      "CSR arrays malformed: row_ptr not monotone / not [0..nnz], column out of range, "
+      "or columns not strictly increasing within a row");
+  if (f & F_SELF_LOOP) return set_err(g->h, SPHX_E_SELF_LOOP, "graph has a self-loop");
+  if (f & F_BAD_WEIGHT) return set_err(g->h, SPHX_E_BAD_WEIGHT,
+      "edge weight not finite and > 0, or vertex weight < 1");
+  if (f & F_NOT_SYM) return set_err(g->h, SPHX_E_NOT_SYMMETRIC,
+      "pattern or weights not symmetric");
+  return SPHX_OK;
+}
+
+constexpr int kDegBlocks = 1024;
+
+int compute_degrees(sphx_graph *g, double *d64, float *d32, void *scratch,
+                    DegreeStats *out, void *pinned, hipStream_t s) {
+  double *stats = static_cast<double *>(scratch);
+  double *host = static_cast<double *>(pinned);
+  // edge-weight range: e0 of the exact degree sums and of the exact cut
+  if (g->wdt != SPHX_UNIT && !g->stats_valid) {
+    unsigned gw = grid_for(g->nnz, 256, 1024);
+    if (g->wdt == SPHX_F32)
+      hipLaunchKernelGGL((k_wrange<float>), dim3(gw), dim3(256), 0, s, g->nnz,
+                         (const float *)g->w, stats);
+    else
+      hipLaunchKernelGGL((k_wrange<double>), dim3(gw), dim3(256), 0, s, g->nnz,
+                         (const double *)g->w, stats);
+    SPHX_HIP(g->h, hipGetLastError());
+    SPHX_HIP(g->h, hipMemcpyAsync(host, stats, sizeof(double) * 2 * gw,
+                                  hipMemcpyDeviceToHost, s));
+    SPHX_HIP(g->h, hipStreamSynchronize(s));
+    double a = 0, b = 1e300;
+    for (unsigned q = 0; q < gw; ++q) {
+      a = std::max(a, host[q * 2]);
+      b = std::min(b, host[q * 2 + 1]);
+    }
+    g->wmax = a;
+    g->wmin = b;
+    int ea, eb;
+    std::frexp(a, &ea);
+    std::frexp(b, &eb);
+    if (g->nnz > 0 && ea - eb > 40)
+      return set_err(g->h, SPHX_E_BAD_WEIGHT,
+                     "edge weights span more than a factor 2^40 (exact sums unsupported)");
+  }
+  int e0 = 0;
+  if (g->wdt == SPHX_F32) e0 = fixed_exponent<float>(g->wmin);
+  if (g->wdt == SPHX_F64) e0 = fixed_exponent<double>(g->wmin);
+  unsigned gb = grid_for(g->n, 4, kDegBlocks);
+  with_types(g, [&](auto it, auto wt) {
+    using IdxT = decltype(it);
+    using WT = decltype(wt);
+    hipLaunchKernelGGL((k_degrees<IdxT, WT>), dim3(gb), dim3(256), 0, s, g->n,
+                       (const IdxT *)g->rowptr, (const WT *)g->w, e0, d64, d32, stats);
+  });
+  SPHX_HIP(g->h, hipGetLastError());
+  SPHX_HIP(g->h, hipMemcpyAsync(host, stats, sizeof(double) * 4 * gb,
+                                hipMemcpyDeviceToHost, s));
+  SPHX_HIP(g->h, hipStreamSynchronize(s));
+  double mx = 0, mn = 1e300, wmx = 0, wmn = 1e300;
+  for (unsigned b = 0; b < gb; ++b) {
+    mx = std::max(mx, host[b * 4 + 0]);
+    mn = std::min(mn, host[b * 4 + 1]);
+    wmx = std::max(wmx, host[b * 4 + 2]);
+    wmn = std::min(wmn, host[b * 4 + 3]);
+  }
+  out->max_deg = (int64_t)mx;
+  out->min_deg = (int64_t)mn;
+  out->sum_deg = g->nnz;
+  out->max_wdeg = wmx;
+  out->min_wdeg = wmn;
+  g->max_deg = out->max_deg;
+  g->sum_deg = out->sum_deg;
+  g->max_wdeg = wmx;
+  g->stats_valid = 1;
+  return SPHX_OK;
+}
+
+size_t plan_bytes(sphx_graph *g) {
+  int64_t n = g->n;
+  int64_t nb = ceil_div(n, kBinRows);
+  int64_t max_hub = g->nnz / kHubDeg + 1;
+  int64_t max_chunks = g->nnz / kHubChunk + max_hub + 1;
+  size_t b = 0;
+  b += align_up(sizeof(int32_t) * n, 256) * 2;          // short + mid lists
+  b += align_up(sizeof(int32_t) * (max_hub + 1), 256);  // hub list
+  b += align_up(sizeof(int32_t) * (max_hub + 1), 256);  // hub chunk begin
+  b += align_up(sizeof(int64_t) * max_chunks, 256) * 2; // chunk ranges
+  b += align_up(sizeof(double) * max_chunks * kMaxNev, 256);
+  b += align_up(sizeof(int) * (nb * 3 + 3), 256);
+  return b + 4096;
+}
+
+int build_plan(sphx_graph *g, Arena &ws, SpmmPlan *plan, const DegreeStats &st,
+               void *pinned, hipStream_t s) {
+  *plan = SpmmPlan{};
+  int64_t n = g->n;
+  int64_t nb = ceil_div(n, kBinRows);
+  int64_t max_hub = g->nnz / kHubDeg + 1;
+  int64_t max_chunks = g->nnz / kHubChunk + max_hub + 1;
+  int32_t *l0 = ws.take<int32_t>(n);
+  int32_t *l1 = ws.take<int32_t>(n);
+  int32_t *l2 = ws.take<int32_t>(max_hub + 1);
+  int32_t *hcb = ws.take<int32_t>(max_hub + 1);
+  int64_t *k0 = ws.take<int64_t>(max_chunks);
+  int64_t *k1 = ws.take<int64_t>(max_chunks);
+  double *hp = ws.take<double>(max_chunks * kMaxNev);
+  int *counts = ws.take<int>(nb * 3 + 3);
+  if (st.max_deg <= kShortDeg) return SPHX_OK;   // natural order, one kernel
+  plan->binned = true;
+  int *totals = counts + nb * 3;
+  if (g->rp64) {
+    hipLaunchKernelGGL((k_bin_count<int64_t>), dim3(nb), dim3(256), 0, s, n,
+                       (const int64_t *)g->rowptr, counts);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1), 0, s, (int)nb, counts, totals);
+    hipLaunchKernelGGL((k_bin_scatter<int64_t>), dim3(nb), dim3(256), 0, s, n,
+                       (const int64_t *)g->rowptr, counts, l0, l1, l2);
+  } else {
+    hipLaunchKernelGGL((k_bin_count<int32_t>), dim3(nb), dim3(256), 0, s, n,
+                       (const int32_t *)g->rowptr, counts);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1), 0, s, (int)nb, counts, totals);
+    hipLaunchKernelGGL((k_bin_scatter<int32_t>), dim3(nb), dim3(256), 0, s, n,
+                       (const int32_t *)g->rowptr, counts, l0, l1, l2);
+  }
+  SPHX_HIP(g->h, hipGetLastError());
+  int *th = static_cast<int *>(pinned);
+  SPHX_HIP(g->h, hipMemcpyAsync(th, totals, sizeof(int) * 3, hipMemcpyDeviceToHost, s));
+  SPHX_HIP(g->h, hipStreamSynchronize(s));
+  plan->short_rows = l0;
+  plan->n_short = th[0];
+  plan->mid_rows = l1;
+  plan->n_mid = th[1];
+  plan->hub_rows = l2;
+  plan->n_hub = th[2];
+  plan->hub_chunk_begin = hcb;
+  plan->chunk_k0 = k0;
+  plan->chunk_k1 = k1;
+  plan->hub_partial = hp;
+  if (plan->n_hub > 0) {
+    // chunk table on the host (hub rows are few)
+    int64_t nh = plan->n_hub;
+    std::vector<int32_t> rows(nh);
+    SPHX_HIP(g->h, hipMemcpyAsync(rows.data(), l2, sizeof(int32_t) * nh,
+                                  hipMemcpyDeviceToHost, s));
+    std::vector<int64_t> rb(nh), re(nh);
+    SPHX_HIP(g->h, hipStreamSynchronize(s));
+    size_t esz = g->rp64 ? 8 : 4;
+    for (int64_t q = 0; q < nh; ++q) {
+      int64_t i = rows[q];
+      int64_t pair[2] = {0, 0};
+      if (g->rp64) {
+        SPHX_HIP(g->h, hipMemcpy(pair, (const char *)g->rowptr + esz * i, 16,
+                                 hipMemcpyDeviceToHost));
+      } else {
+        int32_t p32[2];
+        SPHX_HIP(g->h, hipMemcpy(p32, (const char *)g->rowptr + esz * i, 8,
+                                 hipMemcpyDeviceToHost));
+        pair[0] = p32[0];
+        pair[1] = p32[1];
+      }
+      rb[q] = pair[0];
+      re[q] = pair[1];
+    }
+    std::vector<int32_t> begin(nh + 1);
+    std::vector<int64_t> c0, c1;
+    for (int64_t q = 0; q < nh; ++q) {
+      begin[q] = (int32_t)c0.size();
+      for (int64_t k = rb[q]; k < re[q]; k += kHubChunk) {
+        c0.push_back(k);
+        c1.push_back(std::min<int64_t>(k + kHubChunk, re[q]));
+      }
+    }
+    begin[nh] = (int32_t)c0.size();
+    plan->n_chunks = (int64_t)c0.size();
+    SPHX_HIP(g->h, hipMemcpyAsync(hcb, begin.data(), sizeof(int32_t) * (nh + 1),
+                                  hipMemcpyHostToDevice, s));
+    SPHX_HIP(g->h, hipMemcpyAsync(k0, c0.data(), sizeof(int64_t) * c0.size(),
+                                  hipMemcpyHostToDevice, s));
+    SPHX_HIP(g->h, hipMemcpyAsync(k1, c1.data(), sizeof(int64_t) * c1.size(),
+                                  hipMemcpyHostToDevice, s));
+    SPHX_HIP(g->h, hipStreamSynchronize(s));
+  }
+  return SPHX_OK;
+}
+
+}  // namespace sphx

@@ -1,0 +1,121 @@
+"""Split and quality on the GPU vs the oracle: bit-exact part vectors, cut,
+part weights and imbalance (integer / exactly rounded results)."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import paper_2105_00578_amd as sx
+from oracle import quality, split
+from tests.gpu_util import dev, random_graph, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def handle():
+    return sx.Handle(0)
+
+
+def _grid(s):
+    n, (u, v) = graphgen.grid2d_5pt(s, s)
+    return graphgen.csr_from_edges(n, u, v)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("K", [2, 8, 64, 1024])
+@pytest.mark.parametrize("ties", [False, True])
+def test_split_bit_exact(handle, dtype, K, ties):
+    g = _grid(50)                          # n = 2500 (coordinates only matter)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    rng = np.random.default_rng(K)
+    coords = rng.standard_normal((g.n, 4))
+    if ties:
+        coords = np.round(coords, 1)       # many exact ties, including -0.0 / +0.0
+    coords = coords.astype(dtype)
+    part = sx.split(handle, G, torch.from_numpy(coords).to(dev()), K).cpu().numpy()
+    ref = split.split_pow2(coords, K)
+    assert np.array_equal(part, ref)
+
+
+def test_split_weighted_and_strided(handle):
+    g = random_graph(3000, 0.001, 2)
+    rng = np.random.default_rng(1)
+    vw = rng.integers(1, 20, g.n).astype(np.int32)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w, vwgt=torch.from_numpy(vw).to(dev()))
+    V = rng.standard_normal((g.n, 5)).astype(np.float32)
+    Vd = torch.from_numpy(V).to(dev())
+    # embedding = columns 1..4 of a 5-wide block (row stride 5)
+    part = sx.split(handle, G, Vd[:, 1:], 16, ld=5, ncoord=4).cpu().numpy()
+    assert np.array_equal(part, split.split_pow2(V[:, 1:], 16, vw))
+
+
+def test_split_nan_rejected(handle):
+    g = _grid(10)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    c = torch.zeros((g.n, 1), dtype=torch.float64, device=dev())
+    c[5, 0] = float("nan")
+    with pytest.raises(sx.SphynxError) as e:
+        sx.split(handle, G, c, 4)
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("kind", ["unit", "f32", "f64"])
+def test_quality_exact(handle, kind):
+    wd = {"unit": None, "f32": np.float32, "f64": np.float64}[kind]
+    g = random_graph(2000, 0.01, 9, wd)
+    vw = np.random.default_rng(3).integers(1, 5, g.n).astype(np.int32)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w, vwgt=torch.from_numpy(vw).to(dev()))
+    K = 7
+    part = np.random.default_rng(4).integers(0, K, g.n).astype(np.int32)
+    cut, cut2, imb, pw = sx.quality(handle, G, torch.from_numpy(part).to(dev()), K)
+    c_ref, c2_ref = quality.cutsize(g.rowptr, g.col, g.w, part)
+    assert cut == c_ref and cut2 == c2_ref
+    assert list(pw) == list(quality.part_weights(part, K, vw))
+    assert imb == quality.imbalance(part, K, vw)
+
+
+def test_quality_grid_closed_forms(handle):
+    g = graphgen.config_graph("grid64")
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    x = np.arange(g.n) % 64
+    y = np.arange(g.n) // 64
+    quad = ((x >= 32).astype(np.int32) + 2 * (y >= 32)).astype(np.int32)
+    cut, cut2, imb, pw = sx.quality(handle, G, torch.from_numpy(quad).to(dev()), 4)
+    assert (cut, cut2, imb) == (128.0, 256.0, 1.0)
+
+
+def test_quality_bad_part_rejected(handle):
+    g = _grid(10)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    p = torch.zeros(g.n, dtype=torch.int32, device=dev())
+    p[3] = 9
+    with pytest.raises(sx.SphynxError):
+        sx.quality(handle, G, p, 4)
+
+
+@pytest.mark.parametrize("prec", [sx.FP64, sx.MIXED])
+def test_partition_end_to_end_grid64(handle, prec):
+    """Algorithm 2 on the 64x64 grid, K = 4: the part vector equals the oracle
+    split of the GPU's own eigenvectors, and cut / imbalance equal the oracle's."""
+    g = graphgen.config_graph("grid64")
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    opts = sx.Options(precond=sx.PRECOND_JACOBI, tol=1e-6 if prec == sx.FP64 else 1e-4,
+                      precision=prec)
+    lam, V, part, cut, imb, st = sx.partition(handle, G, 4, opts)
+    Vh = V.cpu().numpy()
+    p_ref = split.split_pow2(Vh[:, 1:], 4)
+    ph = part.cpu().numpy()
+    assert np.array_equal(ph, p_ref)
+    c_ref, _ = quality.cutsize(g.rowptr, g.col, None, p_ref)
+    assert cut == c_ref
+    assert imb == quality.imbalance(p_ref, 4) == 1.0
+    # a good spectral split of the grid: close to the straight quadrant cut
+    assert cut <= 1.6 * 128

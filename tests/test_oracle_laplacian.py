@@ -53,6 +53,13 @@ def test_degrees_bruteforce():
     assert np.allclose(lap.degrees(g.rowptr, g.col, g.w), d, rtol=1e-14)
 
 
+def test_degrees_are_exactly_rounded():
+    # vertex 1 has weights 2^53, 1, 1: a left-to-right float sum gives 2^53
+    g = graphgen.csr_from_edges(4, np.array([0, 1, 1]), np.array([1, 2, 3]),
+                                np.array([2.0 ** 53, 1.0, 1.0]))
+    assert lap.degrees(g.rowptr, g.col, g.w)[1] == 2.0 ** 53 + 2.0
+
+
 @pytest.mark.parametrize("n", [7, 32])
 def test_path_closed_form_eigenvectors(n):
     u = np.arange(n - 1)

@@ -254,6 +254,31 @@ int sphx_eig_backward(sphx_handle *h, sphx_graph *g, int problem, int nev,
                       const double *g_vals, const void *g_vecs,
                       double cg_tol, int cg_max_iter, void *grad_w);
 
+/* ------------------------------------------------------- kernel test hooks */
+/* The dense kernels of one LOBPCG iteration (Algorithm 1: the block Gram
+ * products and RR(S, nev)), exposed so that tests can check them alone.
+ *
+ * sphx_block_gram: Gram matrices of the basis S = [X, H_a, P_a] (a = the nact
+ * columns listed in act, host int32; H_a only if use_h, P_a only if use_p):
+ * GA = S^T [LX, LH_a, LP_a] and GB = S^T B S with B = diag(bdiag) (device
+ * double[n]) or I (NULL).  X, LX, H, LH, P, LP: device n x m blocks of dtype
+ * (unused ones may be NULL).  GA, GB: host double[w*w], w = m + nact*(use_h +
+ * use_p), row-major; accumulated in FP64 on the matrix cores.
+ *
+ * sphx_rayleigh_ritz: Ritz pairs of the w x w pencil (GA, GB) (host, only the
+ * upper triangle i <= j is read), the m smallest: Y host double[w*m]
+ * (row-major, columns GB-orthonormal), theta host double[m] ascending.
+ * Basis columns from p_begin on are dropped if the pencil is numerically
+ * rank deficient (kept < m); kept and breakdown (host int) report the rank
+ * used and whether fewer than m directions remained. */
+int sphx_block_gram(sphx_handle *h, int64_t n, int m, int dtype, const void *X,
+                    const void *LX, const void *H, const void *LH, const void *P,
+                    const void *LP, int nact, const int32_t *act, int use_h,
+                    int use_p, const double *bdiag, double *GA, double *GB);
+int sphx_rayleigh_ritz(sphx_handle *h, int m, int w, int p_begin,
+                       double drop_tol, const double *GA, const double *GB,
+                       double *Y, double *theta, int *kept, int *breakdown);
+
 #ifdef __cplusplus
 }
 #endif

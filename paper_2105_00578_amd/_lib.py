@@ -77,6 +77,10 @@ def _load():
                                      dp, dp, C.POINTER(_Stats)]),
         "sphx_eig_backward": (C.c_int, [vp, vp, C.c_int, C.c_int, dp, vp, dp, vp, C.c_double,
                                         C.c_int, vp]),
+        "sphx_block_gram": (C.c_int, [vp, i64, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp,
+                                      C.c_int, i32p, C.c_int, C.c_int, vp, dp, dp]),
+        "sphx_rayleigh_ritz": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_double, dp, dp,
+                                         dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -85,7 +89,19 @@ def _load():
     return L
 
 
-lib = _load()
+class _LazyLib:
+    """Loads libsphynx.so on first use (so that the build step can import this
+    package before the library exists); raises ImportError if it is missing."""
+
+    _L = None
+
+    def __getattr__(self, name):
+        if _LazyLib._L is None:
+            _LazyLib._L = _load()
+        return getattr(_LazyLib._L, name)
+
+
+lib = _LazyLib()
 
 
 def status_string(code: int) -> str:
@@ -373,3 +389,41 @@ def eig_backward(h: Handle, g: Graph, problem: int, eigvals, V, g_vals=None, g_v
                                  C.c_void_p(_ptr(grad)))
     h._check(code, allow_warn=allow_not_converged)
     return grad
+
+
+def block_gram(h: Handle, X, LX, H=None, LH=None, P=None, LP=None, act=(), bdiag=None):
+    """Test hook: (GA, GB) of S = [X, H_a, P_a] as numpy w x w arrays."""
+    import numpy as np
+    n, m = X.shape
+    act = list(act)
+    use_h = H is not None
+    use_p = P is not None
+    w = m + len(act) * (int(use_h) + int(use_p))
+    GA = np.zeros((w, w))
+    GB = np.zeros((w, w))
+    acts = (C.c_int32 * max(1, len(act)))(*act)
+    dp = C.POINTER(C.c_double)
+    h._check(lib.sphx_block_gram(
+        h.h, n, m, _dtype_code(X), C.c_void_p(_ptr(X)), C.c_void_p(_ptr(LX)),
+        C.c_void_p(_ptr(H)), C.c_void_p(_ptr(LH)), C.c_void_p(_ptr(P)), C.c_void_p(_ptr(LP)),
+        len(act), acts, int(use_h), int(use_p), C.c_void_p(_ptr(bdiag)),
+        GA.ctypes.data_as(dp), GB.ctypes.data_as(dp)))
+    return GA, GB
+
+
+def rayleigh_ritz(h: Handle, m: int, GA, GB, p_begin=None, drop_tol: float = 1e-14):
+    """Test hook: (Y, theta, kept, breakdown) of the pencil (GA, GB)."""
+    import numpy as np
+    w = GA.shape[0]
+    GA = np.ascontiguousarray(GA, dtype=np.float64)
+    GB = np.ascontiguousarray(GB, dtype=np.float64)
+    Y = np.zeros((w, m))
+    th = np.zeros(m)
+    kept = C.c_int()
+    bd = C.c_int()
+    dp = C.POINTER(C.c_double)
+    h._check(lib.sphx_rayleigh_ritz(h.h, m, w, w if p_begin is None else p_begin, drop_tol,
+                                    GA.ctypes.data_as(dp), GB.ctypes.data_as(dp),
+                                    Y.ctypes.data_as(dp), th.ctypes.data_as(dp),
+                                    C.byref(kept), C.byref(bd)))
+    return Y, th, kept.value, bd.value

@@ -131,6 +131,15 @@ __global__ void k_inverse(const double *d, double *dinv, int64_t n) {
     dinv[i] = 1.0 / d[i];
 }
 
+// out[i, c] = scale * dinv[i] * in[i, c]
+template <typename T>
+__global__ void k_scale_rows(const T *in, const double *dinv, double scale, T *out, int64_t n,
+                             int m) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * m;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = T(scale * dinv[e / m] * double(in[e]));
+}
+
 template <typename T>
 __global__ void k_jacobi(const T *R, const double *d, T *H, int64_t n, int m) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * m;
@@ -199,13 +208,24 @@ int cheb_apply(sphx_graph *g, const SpmmPlan &plan, int m, const ColMap &cm, con
     e.dinv = dinv;
     return e;
   };
-  SPHX_TRY(spmm_cheb<T>(g, plan, R, m, cm, epi(nullptr, 1.0, B1, 1.0 / k.c, 0), s));
+  // h1 = rhs / c: rhs = r (combinatorial), read from R with a scale; or
+  // rhs = D^-1 r (generalized), materialised in B2 first.
+  const T *h1 = R;
+  double h1_scale = 1.0 / k.c;
+  if (dinv) {
+    hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for((int64_t)g->n * m, 256, 4096)),
+                       dim3(256), 0, s, R, dinv, 1.0 / k.c, B2, g->n, m);
+    h1 = B2;
+    h1_scale = 1.0;
+  }
+  SPHX_TRY(spmm_cheb<T>(g, plan, h1, m, cm, epi(nullptr, 1.0, B1, h1_scale, 0), s));
   ++*calls;
   T *cur = B1, *other = B2;
   const int deg = (int)k.alpha.size();
   if (deg >= 2) {
-    // step 2: the previous iterate h1 = r / c is read from R with a scale
-    SPHX_TRY(spmm_cheb<T>(g, plan, B1, m, cm, epi(R, 1.0 / k.c, B2, 1.0, 1), s));
+    // step 2: the previous iterate is h1 (in R with a scale, or in B2,
+    // which is then overwritten in place by h3)
+    SPHX_TRY(spmm_cheb<T>(g, plan, B1, m, cm, epi(h1, h1_scale, B2, 1.0, 1), s));
     ++*calls;
     cur = B2;
     other = B1;
@@ -758,6 +778,89 @@ int sphx_quality(sphx_handle *h, sphx_graph *g, const int32_t *part, int K, doub
   if (r != SPHX_OK) return set_err(h, r, err);
   if (cut) *cut = c;
   if (cut2x) *cut2x = 2.0 * c;
+  return SPHX_OK;
+}
+
+int sphx_block_gram(sphx_handle *h, int64_t n, int m, int dtype, const void *X,
+                    const void *LX, const void *H, const void *LH, const void *P,
+                    const void *LP, int nact, const int32_t *act, int use_h, int use_p,
+                    const double *bdiag, double *GA, double *GB) {
+  if (!h || n < 1 || m < 1 || m > kMaxNev || nact < 0 || nact > m || !X || !LX || !GA ||
+      !GB || (dtype != SPHX_F32 && dtype != SPHX_F64) || (nact > 0 && !act))
+    return SPHX_E_INVALID_ARG;
+  if ((use_h && (!H || !LH)) || (use_p && (!P || !LP))) return SPHX_E_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  char *ws = nullptr;
+  size_t need = sizeof(double) * (gram_partial_doubles(kGramBlocks) + 2 * kMaxW * kMaxW) + 1024;
+  SPHX_TRY(get_workspace(h, need, &ws));
+  double *parts = reinterpret_cast<double *>(ws);
+  double *out = parts + gram_partial_doubles(kGramBlocks);
+  GramArgs a{n, m, identity_map(m), use_h, use_p, bdiag};
+  a.act.count = nact;
+  for (int q = 0; q < nact; ++q) {
+    if (act[q] < 0 || act[q] >= m) return SPHX_E_INVALID_ARG;
+    a.act.col[q] = act[q];
+  }
+  int st = dtype == SPHX_F32
+               ? gram<float>((const float *)X, (const float *)LX, (const float *)H,
+                             (const float *)LH, (const float *)P, (const float *)LP, a, parts,
+                             kGramBlocks, out, h->stream)
+               : gram<double>((const double *)X, (const double *)LX, (const double *)H,
+                              (const double *)LH, (const double *)P, (const double *)LP, a,
+                              parts, kGramBlocks, out, h->stream);
+  if (st != SPHX_OK) return set_err(h, st, "gram launch failed");
+  std::vector<double> host(2 * kMaxW * kMaxW);
+  SPHX_HIP(h, hipMemcpyAsync(host.data(), out, sizeof(double) * host.size(),
+                             hipMemcpyDeviceToHost, h->stream));
+  SPHX_HIP(h, hipStreamSynchronize(h->stream));
+  const int w = m + (nact > 0 ? nact * ((use_h ? 1 : 0) + (use_p ? 1 : 0)) : 0);
+  for (int i = 0; i < w; ++i)
+    for (int j = 0; j < w; ++j) {
+      int lo = std::min(i, j), hi = std::max(i, j);
+      GA[i * w + j] = host[lo * kMaxW + hi];
+      GB[i * w + j] = host[kMaxW * kMaxW + lo * kMaxW + hi];
+    }
+  return SPHX_OK;
+}
+
+int sphx_rayleigh_ritz(sphx_handle *h, int m, int w, int p_begin, double drop_tol,
+                       const double *GA, const double *GB, double *Y, double *theta,
+                       int *kept, int *breakdown) {
+  if (!h || m < 1 || m > kMaxNev || w < m || w > kMaxW || p_begin < m || p_begin > w ||
+      !GA || !GB || !Y || !theta || !(drop_tol > 0))
+    return SPHX_E_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  char *ws = nullptr;
+  size_t need = sizeof(double) * (2 * kMaxW * kMaxW + kMaxW * kMaxNev + kMaxNev) +
+                sizeof(DevStatus) + 2048;
+  SPHX_TRY(get_workspace(h, need, &ws));
+  Arena a;
+  a.base = ws;
+  double *g = a.take<double>(2 * kMaxW * kMaxW);
+  double *Yd = a.take<double>(kMaxW * kMaxNev);
+  double *th = a.take<double>(kMaxNev);
+  DevStatus *st = a.take<DevStatus>(1);
+  std::vector<double> host(2 * kMaxW * kMaxW, 0.0);
+  for (int i = 0; i < w; ++i)
+    for (int j = i; j < w; ++j) {
+      host[i * kMaxW + j] = GA[i * w + j];
+      host[kMaxW * kMaxW + i * kMaxW + j] = GB[i * w + j];
+    }
+  SPHX_HIP(h, hipMemcpyAsync(g, host.data(), sizeof(double) * host.size(),
+                             hipMemcpyHostToDevice, h->stream));
+  launch_rr(g, RRArgs{m, w, p_begin, drop_tol}, Yd, th, st, h->stream);
+  SPHX_HIP(h, hipGetLastError());
+  std::vector<double> yh(kMaxW * kMaxNev);
+  DevStatus sh;
+  SPHX_HIP(h, hipMemcpyAsync(yh.data(), Yd, sizeof(double) * yh.size(), hipMemcpyDeviceToHost,
+                             h->stream));
+  SPHX_HIP(h, hipMemcpyAsync(theta, th, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));
+  SPHX_HIP(h, hipMemcpyAsync(&sh, st, sizeof(DevStatus), hipMemcpyDeviceToHost, h->stream));
+  SPHX_HIP(h, hipStreamSynchronize(h->stream));
+  for (int i = 0; i < w; ++i)
+    for (int c = 0; c < m; ++c) Y[i * m + c] = yh[i * kMaxNev + c];
+  if (kept) *kept = sh.kept;
+  if (breakdown) *breakdown = sh.breakdown;
   return SPHX_OK;
 }
 

@@ -170,15 +170,15 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, const T *__restrict__ X
     }
     __syncthreads();
   }
-  // D layout of the 16x16x4 FP64 product: lane holds rows 4*(lane/16)+r,
-  // column lane%16.
+  // D layout of the 16x16x4 FP64 product: accumulator register r of a lane
+  // holds row 4*r + lane/16, column lane%16.
   double *out = partials + (int64_t)blockIdx.x * 2 * W * W;
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
     if (tmat[q] < 0) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int gi = tti[q] * 16 + 4 * k4 + r;
+      int gi = tti[q] * 16 + 4 * r + k4;
       int gj = ttj[q] * 16 + i16;
       out[(int64_t)tmat[q] * W * W + gi * W + gj] = acc[q][r];
     }

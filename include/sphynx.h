@@ -106,9 +106,18 @@ typedef struct sphx_stats {
     double rho[32];       /* final rho_i from one FP64 product L X (first 32) */
     double ms_total;      /* device time of the call (HIP events)             */
     double ms_setup, ms_spmm, ms_precond, ms_gram, ms_rr, ms_update,
-           ms_split, ms_quality;   /* per-phase device time, only when the
-                                      handle's timing flag is on             */
+           ms_split, ms_quality;   /* per-phase device time from HIP events
+                                      around the launches, only when the
+                                      handle's timing flag is on; ms_spmm
+                                      covers the plain and residual Laplacian
+                                      products, ms_precond the Chebyshev
+                                      steps (each a fused Laplacian product)  */
     int64_t spmm_calls;   /* Laplacian products launched (all kinds)         */
+    int64_t precond_calls;     /* Chebyshev steps launched                   */
+    double gb_spmm, gb_precond;  /* algorithmic GB moved by the launches timed
+                                    in ms_spmm / ms_precond: index arrays
+                                    once, each block entry read or written
+                                    once (gathered rows counted once)         */
 } sphx_stats;
 
 /* ---------------------------------------------------------------- basics */

@@ -38,7 +38,9 @@ class _Stats(C.Structure):
                 ("ms_total", C.c_double), ("ms_setup", C.c_double), ("ms_spmm", C.c_double),
                 ("ms_precond", C.c_double), ("ms_gram", C.c_double), ("ms_rr", C.c_double),
                 ("ms_update", C.c_double), ("ms_split", C.c_double),
-                ("ms_quality", C.c_double), ("spmm_calls", C.c_int64)]
+                ("ms_quality", C.c_double), ("spmm_calls", C.c_int64),
+                ("precond_calls", C.c_int64), ("gb_spmm", C.c_double),
+                ("gb_precond", C.c_double)]
 
 
 def _load():
@@ -153,15 +155,19 @@ class Stats:
     avg_degree: float
     rho: list
     ms_total: float
-    ms_split: float
-    ms_quality: float
+    phases_ms: dict
     spmm_calls: int
+    precond_calls: int
+    gb_spmm: float
+    gb_precond: float
 
 
 def _stats(s: _Stats, nev: int) -> Stats:
+    phases = {k: getattr(s, "ms_" + k) for k in
+              ("setup", "spmm", "precond", "gram", "rr", "update", "split", "quality")}
     return Stats(s.iterations, s.converged, s.restarts, s.graph_regular, s.max_degree,
-                 s.avg_degree, list(s.rho[: min(nev, 32)]), s.ms_total, s.ms_split,
-                 s.ms_quality, s.spmm_calls)
+                 s.avg_degree, list(s.rho[: min(nev, 32)]), s.ms_total, phases,
+                 s.spmm_calls, s.precond_calls, s.gb_spmm, s.gb_precond)
 
 
 def _torch():

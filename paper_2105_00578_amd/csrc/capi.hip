@@ -189,11 +189,34 @@ ChebCoef cheb_coef(int degree, double lo, double hi) {
   return k;
 }
 
+// Algorithmic bytes of one Laplacian product over G columns of s-byte
+// values: index arrays once, `vec_passes` block passes (the gathered source
+// counted once), `row_doubles` FP64 per-row values.
+double spmm_bytes(const sphx_graph *g, const SpmmPlan &plan, int G, int s, int vec_passes,
+                  int row_doubles) {
+  double b = (g->rp64 ? 8.0 : 4.0) * double(g->n + 1) + 4.0 * double(g->nnz);
+  if (g->wdt == SPHX_F32) b += 4.0 * double(g->nnz);
+  if (g->wdt == SPHX_F64) b += 8.0 * double(g->nnz);
+  if (plan.binned) b += 4.0 * double(g->n);
+  return b + double(vec_passes) * double(g->n) * G * s + 8.0 * row_doubles * double(g->n);
+}
+
 // H[:, cm] = p(L) R[:, cm]: returns the buffer holding the result.
 template <typename T>
-int cheb_apply(sphx_graph *g, const SpmmPlan &plan, int m, const ColMap &cm, const T *R,
-               T *B1, T *B2, const ChebCoef &k, const double *dinv, hipStream_t s,
-               T **result, int64_t *calls) {
+int cheb_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, const ColMap &cm,
+               const T *R, T *B1, T *B2, const ChebCoef &k, const double *dinv, hipStream_t s,
+               T **result, int64_t *calls, int64_t *pcalls) {
+  const int rd = dinv ? 1 : 0;
+  const double b3 = spmm_bytes(g, plan, cm.count, sizeof(T), 3, rd);
+  const double b4 = spmm_bytes(g, plan, cm.count, sizeof(T), 4, rd);
+  auto launch = [&](const T *src, EpiChebP<T> e, double bytes) -> int {
+    int id = h->plog.begin(PH_PRECOND, bytes, s);
+    int st = spmm_cheb<T>(g, plan, src, m, cm, e, s);
+    h->plog.end(id, s);
+    ++*calls;
+    ++*pcalls;
+    return st;
+  };
   // step 1 gathers h1 = r / c from R directly; h0 = 0
   auto epi = [&](const T *prev, double prev_scale, T *out, double src_scale, int st) {
     EpiChebP<T> e;
@@ -218,22 +241,19 @@ int cheb_apply(sphx_graph *g, const SpmmPlan &plan, int m, const ColMap &cm, con
     h1 = B2;
     h1_scale = 1.0;
   }
-  SPHX_TRY(spmm_cheb<T>(g, plan, h1, m, cm, epi(nullptr, 1.0, B1, h1_scale, 0), s));
-  ++*calls;
+  SPHX_TRY(launch(h1, epi(nullptr, 1.0, B1, h1_scale, 0), b3));
   T *cur = B1, *other = B2;
   const int deg = (int)k.alpha.size();
   if (deg >= 2) {
     // step 2: the previous iterate is h1 (in R with a scale, or in B2,
     // which is then overwritten in place by h3)
-    SPHX_TRY(spmm_cheb<T>(g, plan, B1, m, cm, epi(h1, h1_scale, B2, 1.0, 1), s));
-    ++*calls;
+    SPHX_TRY(launch(B1, epi(h1, h1_scale, B2, 1.0, 1), b4));
     cur = B2;
     other = B1;
     // later steps overwrite the older iterate in place (each element is read
     // and written by the same lane only)
     for (int st = 2; st < deg; ++st) {
-      SPHX_TRY(spmm_cheb<T>(g, plan, cur, m, cm, epi(other, 1.0, other, 1.0, st), s));
-      ++*calls;
+      SPHX_TRY(launch(cur, epi(other, 1.0, other, 1.0, st), b4));
       std::swap(cur, other);
     }
   }
@@ -248,10 +268,12 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
           bool *hit_max) {
   hipStream_t s = h->stream;
   const int64_t n = g->n;
-  int64_t calls = 0;
+  int64_t calls = 0, pcalls = 0;
   Timer tall;
   tall.start(s);
+  PhaseLog &pl = h->plog;
   // ---- setup: degrees, classification, row bins
+  int tid = pl.begin(PH_SETUP, 0.0, s);
   DegreeStats ds;
   SPHX_TRY(compute_degrees(g, w.d64, nullptr, w.deg_scratch, &ds, h->pinned_small, s));
   const bool gen = o.problem == SPHX_GENERALIZED;
@@ -262,6 +284,8 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   pa.base = wsbase + w.plan_off;
   pa.cap = plan_bytes(g);
   SPHX_TRY(build_plan(g, pa, &w.plan, ds, h->pinned_small, s));
+  pl.end(tid, s);
+  const int vs = sizeof(T);
   const double *bdiag = gen ? w.d64 : nullptr;
   const double *dinv = nullptr;
   ChebCoef ck;
@@ -290,23 +314,35 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     launch_init_piecewise<T>(w.X, n, m, s);
   else
     launch_init_random<T>(w.X, n, m, o.seed, s);
+  tid = pl.begin(PH_SPMM, spmm_bytes(g, w.plan, m, vs, 2, 0), s);
   SPHX_TRY(spmm_store<T>(g, w.plan, w.X, m, idm, EpiStoreP<T>{w.LX, m}, s));
+  pl.end(tid, s);
   ++calls;
   GramArgs ga{n, m, idm, 0, 0, bdiag};
   ga.act.count = 0;
+  tid = pl.begin(PH_GRAM, 0.0, s);
   SPHX_TRY(gram<T>(w.X, w.LX, nullptr, nullptr, nullptr, nullptr, ga, w.gram_partials,
                    kGramBlocks, w.gram_out, s));
+  pl.end(tid, s);
+  tid = pl.begin(PH_RR, 0.0, s);
   launch_rr(w.gram_out, RRArgs{m, m, m, drop}, w.Y, w.theta, w.status, s);
+  pl.end(tid, s);
   UpdateArgs ua{n, m, idm, 0, 0};
   ua.act.count = 0;
+  tid = pl.begin(PH_UPDATE, 0.0, s);
   launch_update<T>(w.X, nullptr, w.P, nullptr, w.LP, w.Y, ua, s);
+  pl.end(tid, s);
   const bool jac = o.precond == SPHX_PRECOND_JACOBI;
   auto residual = [&]() -> int {
     int nb = 0;
     EpiResidualP<T> er{w.LX, jac ? w.B1 : w.R, m, w.theta, w.d64, gen ? 1 : 0, jac ? 1 : 0};
+    int id = pl.begin(PH_SPMM, spmm_bytes(g, w.plan, m, vs, 3, 1), s);
     SPHX_TRY(spmm_residual<T>(g, w.plan, w.X, m, idm, er, w.norm_partials, &nb, s));
+    pl.end(id, s);
     ++calls;
+    id = pl.begin(PH_OTHER, 0.0, s);
     launch_finalize(w.norm_partials, nb, m, w.theta, o.tol, o.locking, w.status, s);
+    pl.end(id, s);
     SPHX_HIP(h, hipMemcpyAsync(hs, w.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     SPHX_HIP(h, hipStreamSynchronize(s));
     return SPHX_OK;
@@ -323,21 +359,30 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     for (int q = 0; q < kMaxNev; ++q) act.col[q] = q < hs->nact ? hs->act[q] : 0;
     T *H = w.B1;
     if (o.precond == SPHX_PRECOND_CHEBYSHEV) {
-      SPHX_TRY(cheb_apply<T>(g, w.plan, m, act, w.R, w.B1, w.B2, ck, dinv, s, &H, &calls));
+      SPHX_TRY(cheb_apply<T>(h, g, w.plan, m, act, w.R, w.B1, w.B2, ck, dinv, s, &H, &calls,
+                             &pcalls));
     } else if (o.precond == SPHX_PRECOND_NONE) {
       H = w.R;
     }
+    tid = pl.begin(PH_SPMM, spmm_bytes(g, w.plan, act.count, vs, 2, 0), s);
     SPHX_TRY(spmm_store<T>(g, w.plan, H, m, act, EpiStoreP<T>{w.LH, m}, s));
+    pl.end(tid, s);
     ++calls;
     GramArgs gb{n, m, act, 1, have_p ? 1 : 0, bdiag};
+    tid = pl.begin(PH_GRAM, 0.0, s);
     SPHX_TRY(gram<T>(w.X, w.LX, H, w.LH, w.P, w.LP, gb, w.gram_partials, kGramBlocks,
                      w.gram_out, s));
+    pl.end(tid, s);
     const int na = act.count;
     const int wdt = m + na + (have_p ? na : 0);
+    tid = pl.begin(PH_RR, 0.0, s);
     launch_rr(w.gram_out, RRArgs{m, wdt, have_p ? m + na : wdt, drop}, w.Y, w.theta,
               w.status, s);
+    pl.end(tid, s);
     UpdateArgs ub{n, m, act, 1, have_p ? 1 : 0};
+    tid = pl.begin(PH_UPDATE, 0.0, s);
     launch_update<T>(w.X, H, w.P, w.LH, w.LP, w.Y, ub, s);
+    pl.end(tid, s);
     have_p = true;
     // Jacobi writes the next H into B1, which held this iteration's H (consumed
     // by the update above); Chebyshev and no preconditioner write R.
@@ -399,6 +444,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     stats->converged = nconv;
     stats->restarts = restarts;
     stats->spmm_calls = calls;
+    stats->precond_calls = pcalls;
     stats->ms_total = tall.stop(s);
   } else {
     SPHX_HIP(h, hipStreamSynchronize(s));
@@ -652,16 +698,18 @@ int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int
       dv = dinv;
     }
     ColMap cm = identity_map(m);
-    int64_t calls = 0;
+    int64_t calls = 0, pcalls = 0;
+    h->plog.reset();
+    h->plog.on = false;
     if (dtype == SPHX_F32) {
       float *res = nullptr;
-      SPHX_TRY(cheb_apply<float>(g, plan, m, cm, (const float *)R, (float *)b1, (float *)b2,
-                                 ck, dv, s, &res, &calls));
+      SPHX_TRY(cheb_apply<float>(h, g, plan, m, cm, (const float *)R, (float *)b1,
+                                 (float *)b2, ck, dv, s, &res, &calls, &pcalls));
       SPHX_HIP(h, hipMemcpyAsync(H, res, blk, hipMemcpyDeviceToDevice, s));
     } else {
       double *res = nullptr;
-      SPHX_TRY(cheb_apply<double>(g, plan, m, cm, (const double *)R, (double *)b1,
-                                  (double *)b2, ck, dv, s, &res, &calls));
+      SPHX_TRY(cheb_apply<double>(h, g, plan, m, cm, (const double *)R, (double *)b1,
+                                  (double *)b2, ck, dv, s, &res, &calls, &pcalls));
       SPHX_HIP(h, hipMemcpyAsync(H, res, blk, hipMemcpyDeviceToDevice, s));
     }
   }
@@ -680,6 +728,8 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
     return set_err(h, SPHX_E_INVALID_ARG, "SPHX_INIT_USER needs X0");
   if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
   if (stats) std::memset(stats, 0, sizeof(*stats));
+  h->plog.reset();
+  h->plog.on = h->timing && stats;
   const bool split = part != nullptr;
   char *ws = nullptr;
   SPHX_TRY(get_workspace(h, solve_bytes(g, nev, o->precision, std::max(K, 1), split), &ws));
@@ -698,24 +748,41 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
       Timer ts;
       if (stats) ts.start(h->stream);
       std::string err;
+      int id = h->plog.begin(PH_SPLIT, 0.0, h->stream);
       int r = split_pow2<T>(g, vecs + 1, nev, nev - 1, K, part, w.split_scratch,
                             h->pinned_small, h->stream, &err);
+      h->plog.end(id, h->stream);
       if (r != SPHX_OK) return set_err(h, r, err);
-      if (stats) stats->ms_split = ts.stop(h->stream);
-      Timer tq;
-      if (stats) tq.start(h->stream);
+      id = h->plog.begin(PH_QUALITY, 0.0, h->stream);
       r = quality(g, part, K, cut, imbalance, nullptr, w.quality_scratch, h->pinned_small,
                   h->stream, &err);
+      h->plog.end(id, h->stream);
       if (r != SPHX_OK) return set_err(h, r, err);
-      if (stats) {
-        stats->ms_quality = tq.stop(h->stream);
-        stats->ms_total += stats->ms_split + stats->ms_quality;
-      }
+      if (stats) stats->ms_total += ts.stop(h->stream);
     }
     return SPHX_OK;
   };
   st = o->precision == SPHX_MIXED ? run(float{}) : run(double{});
   if (st < 0) return st;
+  if (stats && h->plog.on) {
+    (void)hipStreamSynchronize(h->stream);
+    double ms[PH_COUNT] = {0}, gb[PH_COUNT] = {0};
+    for (auto &r : h->plog.recs) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) ms[r.phase] += t;
+      gb[r.phase] += r.bytes * 1e-9;
+    }
+    stats->ms_setup = ms[PH_SETUP];
+    stats->ms_spmm = ms[PH_SPMM];
+    stats->ms_precond = ms[PH_PRECOND];
+    stats->ms_gram = ms[PH_GRAM];
+    stats->ms_rr = ms[PH_RR];
+    stats->ms_update = ms[PH_UPDATE];
+    stats->ms_split = ms[PH_SPLIT];
+    stats->ms_quality = ms[PH_QUALITY];
+    stats->gb_spmm = gb[PH_SPMM];
+    stats->gb_precond = gb[PH_PRECOND];
+  }
   return hit_max ? SPHX_NOT_CONVERGED : SPHX_OK;
 }
 

@@ -40,7 +40,52 @@ struct DevStatus {
 
 }  // namespace sphx
 
+namespace sphx {
+// Phase timing with HIP events (recorded around launches, read at the end).
+enum Phase { PH_SETUP, PH_SPMM, PH_PRECOND, PH_GRAM, PH_RR, PH_UPDATE, PH_SPLIT,
+             PH_QUALITY, PH_OTHER, PH_COUNT };
+struct PhaseLog {
+  struct Rec {
+    int phase;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  bool on = false;
+  hipEvent_t take() {
+    if (next == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[next++];
+  }
+  void reset() {
+    recs.clear();
+    next = 0;
+  }
+  // begin/end a timed launch group on stream s
+  int begin(int phase, double bytes, hipStream_t s) {
+    if (!on) return -1;
+    Rec r{phase, bytes, take(), take()};
+    if (!r.a || !r.b) return -1;
+    (void)hipEventRecord(r.a, s);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void end(int id, hipStream_t s) {
+    if (id >= 0) (void)hipEventRecord(recs[id].b, s);
+  }
+  ~PhaseLog() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+}  // namespace sphx
+
 struct sphx_handle {
+  sphx::PhaseLog plog;
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;

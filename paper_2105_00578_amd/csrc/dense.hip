@@ -66,29 +66,18 @@ struct GramDev {
   const double *bdiag;
 };
 
+// Source s of the basis: 0 X, 1 LX, 2 H, 3 LH, 4 P, 5 LP.  Even sources
+// feed S, odd ones L S.  Column c of source s lands at S column
+// off[s/2] + pos, pos = c (X) or the active position of c (H, P).
 template <typename T>
-__device__ __forceinline__ void load_block(double *sS, int wp, const T *__restrict__ src,
-                                           int64_t r0, int64_t n, int m, int off,
-                                           const int *inv) {
-  const int total = kCh * m;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    int row = e / m;
-    int col = e - row * m;
-    int pos = inv ? inv[col] : col;
-    if (pos < 0) continue;
-    int64_t gr = r0 + row;
-    double v = gr < n ? double(src[gr * m + col]) : 0.0;
-    sS[row * wp + off + pos] = v;
-  }
-}
+struct GramSrc {
+  const T *p[6];
+};
+
+constexpr int kPre = (kCh * kMaxNev + 255) / 256;   // staged values per thread and source
 
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void k_gram(GramDev a, const T *__restrict__ X,
-                                              const T *__restrict__ LX,
-                                              const T *__restrict__ H,
-                                              const T *__restrict__ LH,
-                                              const T *__restrict__ P,
-                                              const T *__restrict__ LP,
+__global__ __launch_bounds__(256) void k_gram(GramDev a, GramSrc<T> src,
                                               int64_t rows_per_block, double *partials) {
   constexpr int W = 16 * NT;
   constexpr int WP = W + 1;
@@ -97,11 +86,11 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, const T *__restrict__ X
   __shared__ double sS[kCh * WP];
   __shared__ double sL[kCh * WP];
   __shared__ double sb[kCh];
-  __shared__ int sinv[kMaxNev];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  if (threadIdx.x < kMaxNev) sinv[threadIdx.x] = a.inv[threadIdx.x];
-  for (int e = threadIdx.x; e < kCh * WP; e += blockDim.x) {
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int m = a.m;
+  for (int e = t; e < kCh * WP; e += blockDim.x) {
     sS[e] = 0.0;
     sL[e] = 0.0;
   }
@@ -110,12 +99,12 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, const T *__restrict__ X
   d4 acc[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
-    int t = wave + 4 * q;
+    int tt = wave + 4 * q;
     tmat[q] = -1;
     tti[q] = ttj[q] = 0;
-    if (t < NTILES) {
-      int mat = t / (NT * (NT + 1) / 2);
-      int r = t % (NT * (NT + 1) / 2);
+    if (tt < NTILES) {
+      int mat = tt / (NT * (NT + 1) / 2);
+      int r = tt % (NT * (NT + 1) / 2);
       int ti = 0;
       while (r >= NT - ti) { r -= NT - ti; ++ti; }
       tmat[q] = mat;
@@ -124,27 +113,58 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, const T *__restrict__ X
     }
     acc[q] = d4{0.0, 0.0, 0.0, 0.0};
   }
-  __syncthreads();
+  // per staged slot: destination (row, S column) or -1
+  const bool use[6] = {true, true, a.use_h != 0, a.use_h != 0, a.use_p != 0, a.use_p != 0};
+  const int offs[3] = {0, a.offH, a.offP};
+  int dst[3][kPre];
+#pragma unroll
+  for (int r = 0; r < kPre; ++r) {
+    int e = t + 256 * r;
+    int row = e / m, c = e - row * m;
+    bool in = e < kCh * m;
+    dst[0][r] = in ? row * WP + c : -1;
+    int pos = (in && a.inv[c] >= 0) ? a.inv[c] : -1;
+    dst[1][r] = pos >= 0 ? row * WP + offs[1] + pos : -1;
+    dst[2][r] = pos >= 0 ? row * WP + offs[2] + pos : -1;
+  }
   const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
   const int64_t re = min(a.n, rb + rows_per_block);
+  T st[6][kPre];
+  auto fetch = [&](int64_t r0) {
+    const int64_t base = r0 * m;
+    const int64_t lim = (re - r0) * m;   // valid elements of this chunk
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+#pragma unroll
+      for (int r = 0; r < kPre; ++r) {
+        int e = t + 256 * r;
+        st[s][r] = (use[s] && dst[s >> 1][r] >= 0 && e < lim) ? src.p[s][base + e] : T(0);
+      }
+    }
+  };
   const int i16 = lane & 15;
   const int k4 = lane >> 4;
+  __syncthreads();
+  if (rb < re) fetch(rb);
   for (int64_t r0 = rb; r0 < re; r0 += kCh) {
-    load_block(sS, WP, X, r0, re, a.m, 0, (const int *)nullptr);
-    load_block(sL, WP, LX, r0, re, a.m, 0, (const int *)nullptr);
-    if (a.use_h) {
-      load_block(sS, WP, H, r0, re, a.m, a.offH, sinv);
-      load_block(sL, WP, LH, r0, re, a.m, a.offH, sinv);
+    // stage the fetched chunk into LDS
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      if (!use[s]) continue;
+      double *dstm = (s & 1) ? sL : sS;
+#pragma unroll
+      for (int r = 0; r < kPre; ++r) {
+        int d = dst[s >> 1][r];
+        if (d >= 0) dstm[d] = double(st[s][r]);
+      }
     }
-    if (a.use_p) {
-      load_block(sS, WP, P, r0, re, a.m, a.offP, sinv);
-      load_block(sL, WP, LP, r0, re, a.m, a.offP, sinv);
-    }
-    if (threadIdx.x < kCh) {
-      int64_t gr = r0 + threadIdx.x;
-      sb[threadIdx.x] = gr < re ? (a.bdiag ? a.bdiag[gr] : 1.0) : 0.0;
+    if (t < kCh) {
+      int64_t gr = r0 + t;
+      sb[t] = gr < re ? (a.bdiag ? a.bdiag[gr] : 1.0) : 0.0;
     }
     __syncthreads();
+    // the next chunk's loads overlap the products below
+    if (r0 + kCh < re) fetch(r0 + kCh);
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
       if (tmat[q] < 0) continue;
@@ -185,18 +205,39 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, const T *__restrict__ X
   }
 }
 
-// Sum the block partials of upper tiles in block order.
-__global__ void k_gram_reduce(const double *partials, int nblocks, int NT, double *out) {
+// Sum the block partials of upper tiles in block order: each block takes 16
+// entries, 16 thread groups sum interleaved subsets of the partial blocks,
+// and the 16 subset sums are added in a fixed order.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double *partials, int nblocks,
+                                                     int NT, double *out) {
   const int W = 16 * NT;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * W * W;
-       e += gridDim.x * blockDim.x) {
+  const int E = 2 * W * W;
+  const int t = threadIdx.x;
+  const int e = blockIdx.x * 16 + (t & 15);
+  const int sub = t >> 4;
+  __shared__ double sh[256];
+  double s0 = 0.0, s1 = 0.0;
+  if (e < E) {
+    int ij = e % (W * W);
+    int i = ij / W, j = ij - i * W;
+    if (i / 16 <= j / 16) {
+      int b = sub;
+      for (; b + 16 < nblocks; b += 32) {
+        s0 += partials[(int64_t)b * E + e];
+        s1 += partials[(int64_t)(b + 16) * E + e];
+      }
+      if (b < nblocks) s0 += partials[(int64_t)b * E + e];
+    }
+  }
+  sh[t] = s0 + s1;
+  __syncthreads();
+  if (t < 16 && e < E) {
+    double tot = 0.0;
+    for (int u = 0; u < 16; ++u) tot += sh[u * 16 + t];
     int mat = e / (W * W);
     int ij = e - mat * W * W;
     int i = ij / W, j = ij - i * W;
-    double s = 0.0;
-    if (i / 16 <= j / 16)
-      for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * 2 * W * W + e];
-    out[mat * kMaxW * kMaxW + i * kMaxW + j] = s;
+    out[mat * kMaxW * kMaxW + i * kMaxW + j] = tot;
   }
 }
 
@@ -221,7 +262,9 @@ __device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
   }
   __syncthreads();
   if (k < 2) return;
-  const double abs_floor = 1e-17 * anorm + 1e-300;
+  // rotations stop once off-diagonal entries are at rounding level (a few
+  // ulps of ||A||), or negligible next to both diagonal entries
+  const double abs_floor = 4e-16 * anorm + 1e-300;
   const int kk = k + (k & 1);
   const int npair = kk / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
@@ -237,7 +280,7 @@ __device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
         if (q < k) {
           double apq = A[p * LDA + q];
           double app = A[p * LDA + p], aqq = A[q * LDA + q];
-          if (fabs(apq) > abs_floor && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+          if (fabs(apq) > abs_floor && fabs(apq) > 2e-16 * sqrt(fabs(app * aqq))) {
             double th = (aqq - app) / (2.0 * apq);
             double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             c = 1.0 / sqrt(tt * tt + 1.0);
@@ -464,19 +507,25 @@ __global__ __launch_bounds__(256) void k_update(T *X, const T *__restrict__ H, T
 }
 
 // ------------------------------------------------------------- finalize
-// Sum partials[b][0..2*kMaxNev) over b in a fixed order -> out.
-__device__ void sum_partials_block(const double *partials, int nblocks, double *out) {
-  __shared__ double s[256];
-  const int t = threadIdx.x;
-  const int q = t / 8, l = t % 8;   // 32 sums x 8 lanes
-  double v = 0.0;
-  for (int b = l; b < nblocks; b += 8) v += partials[(int64_t)b * 2 * kMaxNev + q];
-  s[t] = v;
-  __syncthreads();
-  if (l == 0) {
-    double tot = 0.0;
-    for (int u = 0; u < 8; ++u) tot += s[q * 8 + u];
-    out[q] = tot;
+// Sum the sum-major partials (sum q of block b at partials[q * stride + b])
+// over b in a fixed order -> out[q], q < 2 * kMaxNev.  Each wavefront takes
+// every fourth sum: lanes stride over the blocks, then a butterfly.
+__device__ void sum_partials_block(const double *partials, int nblocks, int stride,
+                                   double *out) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int q = wave; q < 2 * kMaxNev; q += 4) {
+    const double *p = partials + (int64_t)q * stride;
+    double v0 = 0.0, v1 = 0.0;
+    int b = lane;
+    for (; b + 64 < nblocks; b += 128) {
+      v0 += p[b];
+      v1 += p[b + 64];
+    }
+    if (b < nblocks) v0 += p[b];
+    double v = v0 + v1;
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) out[q] = v;
   }
   __syncthreads();
 }
@@ -485,7 +534,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, int nb
                                                   int m, const double *theta, double tol,
                                                   int locking, DevStatus *st) {
   __shared__ double sums[2 * kMaxNev];
-  sum_partials_block(partials, nblocks, sums);
+  sum_partials_block(partials, nblocks, kMaxNormBlocks, sums);
   if (threadIdx.x == 0) {
     double floor_th = m > 1 ? theta[1] : theta[0];
     int nconv = 0, na = 0;
@@ -508,14 +557,15 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, int nb
 }
 
 __global__ __launch_bounds__(256) void k_sum_partials(const double *partials, int nblocks,
-                                                      double *out) {
+                                                      int stride, double *out) {
   __shared__ double sums[2 * kMaxNev];
-  sum_partials_block(partials, nblocks, sums);
+  sum_partials_block(partials, nblocks, stride, sums);
   if (threadIdx.x < 2 * kMaxNev) out[threadIdx.x] = sums[threadIdx.x];
 }
 
-// Per-column block sums with a fixed lane -> column assignment.
-__device__ void colsum2(int c, double v1, double v2, int m, double *out) {
+// Per-column block sums with a fixed lane -> column assignment, stored
+// sum-major with stride kRqStride.
+__device__ void colsum2(int c, double v1, double v2, int m, double *partials) {
   __shared__ double s1[256], s2[256];
   __shared__ int sc[256];
   int t = threadIdx.x;
@@ -527,8 +577,8 @@ __device__ void colsum2(int c, double v1, double v2, int m, double *out) {
     double a = 0.0, b = 0.0;
     for (int u = 0; u < (int)blockDim.x; ++u)
       if (sc[u] == t) { a += s1[u]; b += s2[u]; }
-    out[t] = a;
-    out[kMaxNev + t] = b;
+    partials[(int64_t)t * kRqStride + blockIdx.x] = a;
+    partials[(int64_t)(kMaxNev + t) * kRqStride + blockIdx.x] = b;
   }
 }
 
@@ -548,7 +598,7 @@ __global__ __launch_bounds__(256) void k_rq(const T *X, const double *LX, int64_
       a += x * LX[r * m + c];
       b += bd * x * x;
     }
-  colsum2(live ? c : -1, a, b, m, partials + (int64_t)blockIdx.x * 2 * kMaxNev);
+  colsum2(live ? c : -1, a, b, m, partials);
 }
 
 // Residual partials: sum (lx - theta b x)^2 / b and sum b x^2 per column.
@@ -571,7 +621,7 @@ __global__ __launch_bounds__(256) void k_res(const T *X, const double *LX, int64
       b += bd * x * x;
     }
   }
-  colsum2(live ? c : -1, a, b, m, partials + (int64_t)blockIdx.x * 2 * kMaxNev);
+  colsum2(live ? c : -1, a, b, m, partials);
 }
 
 // Column argmax |x| (lowest index on ties): block partials (value, index).
@@ -690,24 +740,25 @@ int gram(const T *X, const T *LX, const T *H, const T *LH, const T *P, const T *
   rows_per_block = ceil_div(rows_per_block, kCh) * kCh;
   int nb = (int)ceil_div(a.n, rows_per_block);
   if (nb < 1) nb = 1;
+  GramSrc<T> sp{{X, LX, H, LH, P, LP}};
   switch (NT) {
     case 1:
-      hipLaunchKernelGGL((k_gram<T, 1>), dim3(nb), dim3(256), 0, s, d, X, LX, H, LH, P, LP,
-                         rows_per_block, partials);
+      hipLaunchKernelGGL((k_gram<T, 1>), dim3(nb), dim3(256), 0, s, d, sp, rows_per_block,
+                         partials);
       break;
     case 2:
-      hipLaunchKernelGGL((k_gram<T, 2>), dim3(nb), dim3(256), 0, s, d, X, LX, H, LH, P, LP,
-                         rows_per_block, partials);
+      hipLaunchKernelGGL((k_gram<T, 2>), dim3(nb), dim3(256), 0, s, d, sp, rows_per_block,
+                         partials);
       break;
     case 3:
-      hipLaunchKernelGGL((k_gram<T, 3>), dim3(nb), dim3(256), 0, s, d, X, LX, H, LH, P, LP,
-                         rows_per_block, partials);
+      hipLaunchKernelGGL((k_gram<T, 3>), dim3(nb), dim3(256), 0, s, d, sp, rows_per_block,
+                         partials);
       break;
     default:
       return SPHX_E_INVALID_ARG;
   }
   int W = 16 * NT;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(grid_for(2 * W * W, 256, 64)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ceil_div(2 * W * W, 16)), dim3(256), 0, s,
                      (const double *)partials, nb, NT, gram_out);
   return hipGetLastError() == hipSuccess ? SPHX_OK : SPHX_E_HIP;
 }
@@ -754,7 +805,7 @@ void launch_res_partials(const T *X, const double *LX, int64_t n, int m, const d
 void launch_sum_partials(const double *partials, int nblocks, int cols, double *out,
                          hipStream_t s) {
   (void)cols;
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, nblocks, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, nblocks, kRqStride, out);
 }
 
 constexpr int kColBlocks = 256;

@@ -69,8 +69,11 @@ struct EpiChebP {
   const double *dinv;  // nullable: 1
 };
 
-// Norm partials: up to kMaxNormBlocks blocks of 2*kMaxNev doubles.
+// Norm partials: 2*kMaxNev sums, each over up to kMaxNormBlocks blocks,
+// stored sum-major (sum q of block b at q * kMaxNormBlocks + b).
 constexpr int kMaxNormBlocks = 4096;
+// Rayleigh-quotient partials: up to kRqStride blocks, sum-major.
+constexpr int kRqStride = 256;
 
 template <typename T>
 int spmm_store(sphx_graph *g, const SpmmPlan &plan, const T *X, int ldx,
@@ -104,7 +107,7 @@ int gram(const T *X, const T *LX, const T *H, const T *LH, const T *P,
          const T *LP, const GramArgs &a, double *partials, int max_blocks,
          double *gram_out, hipStream_t s);
 size_t gram_partial_doubles(int max_blocks);
-constexpr int kGramBlocks = 512;
+constexpr int kGramBlocks = 1024;
 
 // Rayleigh-Ritz on the reduced Gram matrices (one workgroup, FP64).
 // Writes Y (kMaxW x kMaxNev, row-major: Y[k * kMaxNev + c]) and theta

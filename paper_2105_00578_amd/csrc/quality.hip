@@ -13,25 +13,41 @@
 namespace sphx {
 namespace {
 
-// one wavefront per row; each lane accumulates its own exact partial
+// Each thread takes an equal slice of the CSR entries (any degree mix is
+// balanced); the row of its first entry is found by binary search in row_ptr.
+// Each thread accumulates an exact partial.
 template <typename IdxT, typename WT>
-__global__ __launch_bounds__(256) void k_cut(int64_t n, const IdxT *rp, const int32_t *col,
-                                             const WT *w, const int32_t *part, int e0,
+__global__ __launch_bounds__(256) void k_cut(int64_t n, int64_t nnz, const IdxT *rp,
+                                             const int32_t *col, const WT *w,
+                                             const int32_t *part, int e0, int64_t per_thread,
                                              unsigned long long *out) {
-  const int lane = threadIdx.x & 63;
-  const int wpb = blockDim.x / 64;
   U128 acc{0, 0};
-  for (int64_t i = (int64_t)blockIdx.x * wpb + threadIdx.x / 64; i < n;
-       i += (int64_t)gridDim.x * wpb) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k0 = tid * per_thread;
+  const int64_t k1 = min(nnz, k0 + per_thread);
+  if (k0 < k1) {
+    // row i with rp[i] <= k0 < rp[i+1]
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) >> 1;
+      if ((int64_t)rp[mid] <= k0) lo = mid; else hi = mid - 1;
+    }
+    int64_t i = lo;
+    int64_t rend = rp[i + 1];
     int pi = part[i];
-    for (int64_t k = (int64_t)rp[i] + lane; k < (int64_t)rp[i + 1]; k += 64) {
+    for (int64_t k = k0; k < k1; ++k) {
+      while (k >= rend) {
+        ++i;
+        rend = rp[i + 1];
+        pi = part[i];
+      }
       int64_t j = col[k];
       if (j <= i || part[j] == pi) continue;
       if constexpr (std::is_same_v<WT, Unit>) add128(acc, 1ull, 0ull);
       else {
-        unsigned long long lo, hi;
-        fixed_of(w[k], e0, lo, hi);
-        add128(acc, lo, hi);
+        unsigned long long l, h;
+        fixed_of(w[k], e0, l, h);
+        add128(acc, l, h);
       }
     }
   }
@@ -47,13 +63,33 @@ __global__ __launch_bounds__(256) void k_cut(int64_t n, const IdxT *rp, const in
   }
 }
 
-__global__ void k_part_weights(int64_t n, const int32_t *part, const int32_t *vwgt, int K,
-                               unsigned long long *pw, int *bad) {
+// Part weights: integer sums, so the order of the additions does not matter.
+// Up to kLdsParts parts are counted in LDS first (no global contention).
+constexpr int kLdsParts = 4096;
+
+__global__ __launch_bounds__(256) void k_part_weights(int64_t n, const int32_t *part,
+                                                      const int32_t *vwgt, int K,
+                                                      unsigned long long *pw, int *bad) {
+  __shared__ unsigned long long h[kLdsParts];
+  const bool lds = K <= kLdsParts;
+  if (lds) {
+    for (int k = threadIdx.x; k < K; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+  }
+  int f = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     int p = part[i];
-    if (p < 0 || p >= K) { atomicOr(bad, 1); continue; }
-    atomicAdd(&pw[p], (unsigned long long)(vwgt ? vwgt[i] : 1));
+    if (p < 0 || p >= K) { f = 1; continue; }
+    unsigned long long wt = (unsigned long long)(vwgt ? vwgt[i] : 1);
+    if (lds) atomicAdd(&h[p], wt);
+    else atomicAdd(&pw[p], wt);
+  }
+  if (f) atomicOr(bad, 1);
+  if (lds) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += blockDim.x)
+      if (h[k]) atomicAdd(&pw[k], h[k]);
   }
 }
 
@@ -93,14 +129,17 @@ int quality(sphx_graph *g, const int32_t *part, int K, double *cut, double *imba
   if (g->wdt == SPHX_F64) e0 = fixed_exponent<double>(g->wmin);
   hipMemsetAsync(pw, 0, sizeof(unsigned long long) * K, s);
   hipMemsetAsync(bad, 0, sizeof(int) * 4, s);
-  hipLaunchKernelGGL(k_part_weights, dim3(grid_for(g->n, 256, 2048)), dim3(256), 0, s, g->n,
-                     part, g->vwgt, K, pw, bad);
-  unsigned nb = grid_for(g->n, 4, kCutBlocks);
+  hipLaunchKernelGGL(k_part_weights, dim3(grid_for(g->n, 256 * 16, 1024)), dim3(256), 0, s,
+                     g->n, part, g->vwgt, K, pw, bad);
+  unsigned nb = kCutBlocks;
+  const int64_t per_thread = std::max<int64_t>(1, ceil_div(g->nnz, (int64_t)nb * 256));
+  nb = (unsigned)std::max<int64_t>(1, ceil_div(ceil_div(g->nnz, per_thread), 256));
   auto go = [&](auto it, auto wt) {
     using IdxT = decltype(it);
     using WT = decltype(wt);
-    hipLaunchKernelGGL((k_cut<IdxT, WT>), dim3(nb), dim3(256), 0, s, g->n,
-                       (const IdxT *)g->rowptr, g->col, (const WT *)g->w, part, e0, cp);
+    hipLaunchKernelGGL((k_cut<IdxT, WT>), dim3(nb), dim3(256), 0, s, g->n, g->nnz,
+                       (const IdxT *)g->rowptr, g->col, (const WT *)g->w, part, e0,
+                       per_thread, cp);
   };
   if (g->rp64) {
     if (g->wdt == SPHX_UNIT) go(int64_t{}, Unit{});

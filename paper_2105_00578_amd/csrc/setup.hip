@@ -124,6 +124,35 @@ __global__ __launch_bounds__(256) void k_degrees(int64_t n, const IdxT *rp,
   }
 }
 
+// Unit weights: the degree is the row length; one thread per row.
+template <typename IdxT>
+__global__ __launch_bounds__(256) void k_degrees_unit(int64_t n, const IdxT *rp, double *d64,
+                                                      float *d32, double *stats) {
+  double mx = 0.0, mn = 1e300;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = double(rp[i + 1] - rp[i]);
+    d64[i] = s;
+    if (d32) d32[i] = float(s);
+    mx = fmax(mx, s);
+    mn = fmin(mn, s);
+  }
+  __shared__ double sh[2][256];
+  sh[0][threadIdx.x] = mx;
+  sh[1][threadIdx.x] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int t = 1; t < (int)blockDim.x; ++t) {
+      mx = fmax(mx, sh[0][t]);
+      mn = fmin(mn, sh[1][t]);
+    }
+    stats[blockIdx.x * 4 + 0] = mx;
+    stats[blockIdx.x * 4 + 1] = mn;
+    stats[blockIdx.x * 4 + 2] = mx;
+    stats[blockIdx.x * 4 + 3] = mn;
+  }
+}
+
 // edge-weight range (for the exact cut), block partials
 template <typename WT>
 __global__ __launch_bounds__(256) void k_wrange(int64_t nnz, const WT *w, double *stats) {
@@ -300,12 +329,22 @@ int compute_degrees(sphx_graph *g, double *d64, float *d32, void *scratch,
   if (g->wdt == SPHX_F32) e0 = fixed_exponent<float>(g->wmin);
   if (g->wdt == SPHX_F64) e0 = fixed_exponent<double>(g->wmin);
   unsigned gb = grid_for(g->n, 4, kDegBlocks);
-  with_types(g, [&](auto it, auto wt) {
-    using IdxT = decltype(it);
-    using WT = decltype(wt);
-    hipLaunchKernelGGL((k_degrees<IdxT, WT>), dim3(gb), dim3(256), 0, s, g->n,
-                       (const IdxT *)g->rowptr, (const WT *)g->w, e0, d64, d32, stats);
-  });
+  if (g->wdt == SPHX_UNIT) {
+    gb = grid_for(g->n, 256, kDegBlocks);
+    if (g->rp64)
+      hipLaunchKernelGGL((k_degrees_unit<int64_t>), dim3(gb), dim3(256), 0, s, g->n,
+                         (const int64_t *)g->rowptr, d64, d32, stats);
+    else
+      hipLaunchKernelGGL((k_degrees_unit<int32_t>), dim3(gb), dim3(256), 0, s, g->n,
+                         (const int32_t *)g->rowptr, d64, d32, stats);
+  } else {
+    with_types(g, [&](auto it, auto wt) {
+      using IdxT = decltype(it);
+      using WT = decltype(wt);
+      hipLaunchKernelGGL((k_degrees<IdxT, WT>), dim3(gb), dim3(256), 0, s, g->n,
+                         (const IdxT *)g->rowptr, (const WT *)g->w, e0, d64, d32, stats);
+    });
+  }
   SPHX_HIP(g->h, hipGetLastError());
   SPHX_HIP(g->h, hipMemcpyAsync(host, stats, sizeof(double) * 4 * gb,
                                 hipMemcpyDeviceToHost, s));

@@ -113,9 +113,12 @@ struct EpiCheb {
   }
 };
 
-// Per-column block sums of (v1, v2) in a fixed order.  Every thread of the
-// block must call this.  c < 0 marks a lane without a column.
-__device__ void block_colsum(int c, double v1, double v2, int G, double *out) {
+// Per-column block sums of (v1, v2) in a fixed order, stored sum-major:
+// partials[q * kMaxNormBlocks + slot], q = column (v1) or kMaxNev + column
+// (v2).  Every thread of the block must call this.  c < 0 marks a lane
+// without a column.
+__device__ void block_colsum(int c, double v1, double v2, int G, double *partials,
+                             int slot) {
   __shared__ double s1[256], s2[256];
   __shared__ int sc[256];
   int t = threadIdx.x;
@@ -130,8 +133,8 @@ __device__ void block_colsum(int c, double v1, double v2, int G, double *out) {
         a += s1[u];
         b += s2[u];
       }
-    out[t] = a;
-    out[kMaxNev + t] = b;
+    partials[(int64_t)t * kMaxNormBlocks + slot] = a;
+    partials[(int64_t)(kMaxNev + t) * kMaxNormBlocks + slot] = b;
   }
 }
 
@@ -139,7 +142,8 @@ __device__ void block_colsum(int c, double v1, double v2, int G, double *out) {
 template <typename T, typename IdxT, typename WT, typename Epi>
 __global__ __launch_bounds__(256) void k_spmm_group(
     Csr<IdxT, WT> A, const int32_t *__restrict__ rows, int64_t nrows,
-    const T *__restrict__ X, int ldx, ColMap cm, Epi epi, double *partials) {
+    const T *__restrict__ X, int ldx, ColMap cm, Epi epi, double *partials,
+    int slot0) {
   const int G = cm.count;
   const int gpw = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
@@ -160,7 +164,7 @@ __global__ __launch_bounds__(256) void k_spmm_group(
     }
   }
   if constexpr (Epi::kNorms)
-    block_colsum(ok ? c : -1, n1, n2, G, partials + (int64_t)blockIdx.x * 2 * kMaxNev);
+    block_colsum(ok ? c : -1, n1, n2, G, partials, slot0 + (int)blockIdx.x);
 }
 
 // Sum lane values of all groups for column c (result valid in lanes < G).
@@ -179,7 +183,8 @@ __device__ __forceinline__ T group_reduce(T v, int G, int lane) {
 template <typename T, typename IdxT, typename WT, typename Epi>
 __global__ __launch_bounds__(256) void k_spmm_wave(
     Csr<IdxT, WT> A, const int32_t *__restrict__ rows, int64_t nrows,
-    const T *__restrict__ X, int ldx, ColMap cm, Epi epi, double *partials) {
+    const T *__restrict__ X, int ldx, ColMap cm, Epi epi, double *partials,
+    int slot0) {
   const int G = cm.count;
   const int ng = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(256) void k_spmm_wave(
     if (lane < G) epi(i, c, col, xi, tot, n1, n2);
   }
   if constexpr (Epi::kNorms)
-    block_colsum(lane < G ? c : -1, n1, n2, G, partials + (int64_t)blockIdx.x * 2 * kMaxNev);
+    block_colsum(lane < G ? c : -1, n1, n2, G, partials, slot0 + (int)blockIdx.x);
 }
 
 template <typename T, typename IdxT, typename WT>
@@ -239,7 +244,7 @@ template <typename T, typename Epi>
 __global__ __launch_bounds__(256) void k_spmm_hub_combine(
     const int32_t *__restrict__ hub_rows, const int32_t *__restrict__ hub_chunk_begin,
     int64_t n_hub, const double *__restrict__ part, const T *__restrict__ X,
-    int ldx, ColMap cm, Epi epi, double *partials) {
+    int ldx, ColMap cm, Epi epi, double *partials, int slot0) {
   const int G = cm.count;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -259,7 +264,7 @@ __global__ __launch_bounds__(256) void k_spmm_hub_combine(
     }
   }
   if constexpr (Epi::kNorms)
-    block_colsum(c < G ? c : -1, n1, n2, G, partials + (int64_t)blockIdx.x * 2 * kMaxNev);
+    block_colsum(c < G ? c : -1, n1, n2, G, partials, slot0 + (int)blockIdx.x);
 }
 
 // --------------------------------------------------------------- dispatch
@@ -275,24 +280,24 @@ void run_all(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan,
   const int gpw = kWave / G;
   int used = 0;
   auto slot = [&](int blocks) {
-    double *p = partials ? partials + (int64_t)used * 2 * kMaxNev : nullptr;
+    int b = used;
     used += blocks;
-    return p;
+    return b;
   };
   if (!plan.binned) {
     unsigned gb = grid_for(n, 4 * gpw, kGroupBlocks);
     hipLaunchKernelGGL((k_spmm_group<T, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
-                       A, (const int32_t *)nullptr, n, X, ldx, cm, epi, slot(gb));
+                       A, (const int32_t *)nullptr, n, X, ldx, cm, epi, partials, slot(gb));
   } else {
     if (plan.n_short > 0) {
       unsigned gb = grid_for(plan.n_short, 4 * gpw, kGroupBlocks);
       hipLaunchKernelGGL((k_spmm_group<T, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
-                         A, plan.short_rows, plan.n_short, X, ldx, cm, epi, slot(gb));
+                         A, plan.short_rows, plan.n_short, X, ldx, cm, epi, partials, slot(gb));
     }
     if (plan.n_mid > 0) {
       unsigned gb = grid_for(plan.n_mid, 4, kWaveBlocks);
       hipLaunchKernelGGL((k_spmm_wave<T, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
-                         A, plan.mid_rows, plan.n_mid, X, ldx, cm, epi, slot(gb));
+                         A, plan.mid_rows, plan.n_mid, X, ldx, cm, epi, partials, slot(gb));
     }
     if (plan.n_hub > 0) {
       unsigned gb = grid_for(plan.n_chunks, 4, kWaveBlocks);
@@ -303,7 +308,7 @@ void run_all(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan,
       unsigned gc = grid_for(plan.n_hub, 4, kHubBlocks);
       hipLaunchKernelGGL((k_spmm_hub_combine<T, Epi>), dim3(gc), dim3(256), 0, s,
                          plan.hub_rows, plan.hub_chunk_begin, plan.n_hub,
-                         (const double *)plan.hub_partial, X, ldx, cm, epi, slot(gc));
+                         (const double *)plan.hub_partial, X, ldx, cm, epi, partials, slot(gc));
     }
   }
   if (nparts) *nparts = used;

@@ -125,6 +125,8 @@ def test_homogeneity_identities_full_size_grid(handle):
         opts = sx.Options(problem=problem, precond=sx.PRECOND_JACOBI, tol=1e-9,
                           precision=sx.FP64, max_iter=50000)
         lam, V, st = sx.eigensolve(handle, G, 3, opts)
+        from tests.test_gpu_eigensolve import check_rayleigh
+        check_rayleigh(g, problem, lam, V.cpu().numpy(), 1e-10)
         for k in (1, 2):
             e = np.zeros(3); e[k] = 1.0
             grad = sx.eig_backward(handle, G, problem, lam, V, e, None).cpu().numpy()

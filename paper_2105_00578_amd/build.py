@@ -19,7 +19,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsphynx.so")
 ARCH = "gfx950"
 
-SOURCES = ["spmm.hip", "setup.hip", "dense.hip", "split.hip", "quality.hip",
+SOURCES = ["spmm.hip", "spmm_vec.hip", "setup.hip", "dense.hip", "split.hip", "quality.hip",
            "adjoint.hip", "capi.hip"]
 
 FLAGS = [

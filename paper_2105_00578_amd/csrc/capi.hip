@@ -64,7 +64,7 @@ void layout(Arena &a, SolveWs<T> &w, int64_t n, int m, int K, size_t plan_b,
             bool want_split) {
   w.d64 = a.take<double>(n);
   w.dinv = a.take<double>(n);
-  size_t blk = (size_t)n * m;
+  const size_t blk = (size_t)n * padded_ld(m, sizeof(T));
   w.X = a.take<T>(blk);
   w.LX = a.take<T>(blk);
   w.R = a.take<T>(blk);
@@ -94,7 +94,7 @@ void layout(Arena &a, SolveWs<T> &w, int64_t n, int m, int K, size_t plan_b,
   if (want_split) {
     w.split_scratch = a.take<char>(split_scratch_bytes(n, K));
     w.quality_scratch = a.take<char>(quality_scratch_bytes(K));
-    w.V = a.take<T>(blk);
+    w.V = a.take<T>((size_t)n * m);
     w.part = a.take<int32_t>(n);
   } else {
     w.split_scratch = w.quality_scratch = nullptr;
@@ -203,15 +203,20 @@ double spmm_bytes(const sphx_graph *g, const SpmmPlan &plan, int G, int s, int v
 
 // H[:, cm] = p(L) R[:, cm]: returns the buffer holding the result.
 template <typename T>
-int cheb_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, const ColMap &cm,
-               const T *R, T *B1, T *B2, const ChebCoef &k, const double *dinv, hipStream_t s,
-               T **result, int64_t *calls, int64_t *pcalls) {
+int cheb_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, int ld,
+               const ColMap &cm, const T *R, T *B1, T *B2, const ChebCoef &k,
+               const double *dinv, hipStream_t s, T **result, int64_t *calls,
+               int64_t *pcalls) {
   const int rd = dinv ? 1 : 0;
   const double b3 = spmm_bytes(g, plan, cm.count, sizeof(T), 3, rd);
   const double b4 = spmm_bytes(g, plan, cm.count, sizeof(T), 4, rd);
   auto launch = [&](const T *src, EpiChebP<T> e, double bytes) -> int {
     int id = h->plog.begin(PH_PRECOND, bytes, s);
-    int st = spmm_cheb<T>(g, plan, src, m, cm, e, s);
+    // padded rows (the solver's blocks) take the vector-row kernels; the
+    // column-lane kernels serve unpadded caller blocks
+    int st = ld != m || (m * (int)sizeof(T)) % 16 == 0
+                 ? vspmm_cheb<T>(g, plan, src, ld, m, e, s)
+                 : spmm_cheb<T>(g, plan, src, m, cm, e, s);
     h->plog.end(id, s);
     ++*calls;
     ++*pcalls;
@@ -223,7 +228,7 @@ int cheb_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, const
     e.prev = prev;
     e.R = R;
     e.OUT = out;
-    e.ld = m;
+    e.ld = ld;
     e.src_scale = src_scale;
     e.prev_scale = prev_scale;
     e.alpha = k.alpha[st];
@@ -236,8 +241,8 @@ int cheb_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, const
   const T *h1 = R;
   double h1_scale = 1.0 / k.c;
   if (dinv) {
-    hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for((int64_t)g->n * m, 256, 4096)),
-                       dim3(256), 0, s, R, dinv, 1.0 / k.c, B2, g->n, m);
+    hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for((int64_t)g->n * ld, 256, 4096)),
+                       dim3(256), 0, s, R, dinv, 1.0 / k.c, B2, g->n, ld);
     h1 = B2;
     h1_scale = 1.0;
   }
@@ -286,6 +291,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   SPHX_TRY(build_plan(g, pa, &w.plan, ds, h->pinned_small, s));
   pl.end(tid, s);
   const int vs = sizeof(T);
+  const int ld = padded_ld(m, sizeof(T));   // 16-byte rows for the vector kernels
   const double *bdiag = gen ? w.d64 : nullptr;
   const double *dinv = nullptr;
   ChebCoef ck;
@@ -308,17 +314,18 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   const ColMap idm = identity_map(m);
   DevStatus *hs = h->pinned_status;
   // ---- initial block and Rayleigh-Ritz
-  if (o.init == SPHX_INIT_USER)
-    SPHX_HIP(h, hipMemcpyAsync(w.X, X0, sizeof(T) * n * m, hipMemcpyDeviceToDevice, s));
-  else if (o.init == SPHX_INIT_PIECEWISE)
-    launch_init_piecewise<T>(w.X, n, m, s);
+  if (o.init == SPHX_INIT_USER) {
+    SPHX_HIP(h, hipMemsetAsync(w.X, 0, sizeof(T) * n * ld, s));
+    launch_copy_cols<T>(static_cast<const T *>(X0), m, w.X, ld, n, m, s);
+  } else if (o.init == SPHX_INIT_PIECEWISE)
+    launch_init_piecewise<T>(w.X, n, m, ld, s);
   else
-    launch_init_random<T>(w.X, n, m, o.seed, s);
+    launch_init_random<T>(w.X, n, m, ld, o.seed, s);
   tid = pl.begin(PH_SPMM, spmm_bytes(g, w.plan, m, vs, 2, 0), s);
-  SPHX_TRY(spmm_store<T>(g, w.plan, w.X, m, idm, EpiStoreP<T>{w.LX, m}, s));
+  SPHX_TRY(vspmm_store<T>(g, w.plan, w.X, ld, m, EpiStoreP<T>{w.LX, ld}, s));
   pl.end(tid, s);
   ++calls;
-  GramArgs ga{n, m, idm, 0, 0, bdiag};
+  GramArgs ga{n, m, ld, idm, 0, 0, bdiag};
   ga.act.count = 0;
   tid = pl.begin(PH_GRAM, 0.0, s);
   SPHX_TRY(gram<T>(w.X, w.LX, nullptr, nullptr, nullptr, nullptr, ga, w.gram_partials,
@@ -327,7 +334,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   tid = pl.begin(PH_RR, 0.0, s);
   launch_rr(w.gram_out, RRArgs{m, m, m, drop}, w.Y, w.theta, w.status, s);
   pl.end(tid, s);
-  UpdateArgs ua{n, m, idm, 0, 0};
+  UpdateArgs ua{n, m, ld, idm, 0, 0};
   ua.act.count = 0;
   tid = pl.begin(PH_UPDATE, 0.0, s);
   launch_update<T>(w.X, nullptr, w.P, nullptr, w.LP, w.Y, ua, s);
@@ -335,9 +342,9 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   const bool jac = o.precond == SPHX_PRECOND_JACOBI;
   auto residual = [&]() -> int {
     int nb = 0;
-    EpiResidualP<T> er{w.LX, jac ? w.B1 : w.R, m, w.theta, w.d64, gen ? 1 : 0, jac ? 1 : 0};
+    EpiResidualP<T> er{w.LX, jac ? w.B1 : w.R, ld, w.theta, w.d64, gen ? 1 : 0, jac ? 1 : 0};
     int id = pl.begin(PH_SPMM, spmm_bytes(g, w.plan, m, vs, 3, 1), s);
-    SPHX_TRY(spmm_residual<T>(g, w.plan, w.X, m, idm, er, w.norm_partials, &nb, s));
+    SPHX_TRY(vspmm_residual<T>(g, w.plan, w.X, ld, m, er, w.norm_partials, &nb, s));
     pl.end(id, s);
     ++calls;
     id = pl.begin(PH_OTHER, 0.0, s);
@@ -359,16 +366,16 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     for (int q = 0; q < kMaxNev; ++q) act.col[q] = q < hs->nact ? hs->act[q] : 0;
     T *H = w.B1;
     if (o.precond == SPHX_PRECOND_CHEBYSHEV) {
-      SPHX_TRY(cheb_apply<T>(h, g, w.plan, m, act, w.R, w.B1, w.B2, ck, dinv, s, &H, &calls,
+      SPHX_TRY(cheb_apply<T>(h, g, w.plan, m, ld, act, w.R, w.B1, w.B2, ck, dinv, s, &H, &calls,
                              &pcalls));
     } else if (o.precond == SPHX_PRECOND_NONE) {
       H = w.R;
     }
     tid = pl.begin(PH_SPMM, spmm_bytes(g, w.plan, act.count, vs, 2, 0), s);
-    SPHX_TRY(spmm_store<T>(g, w.plan, H, m, act, EpiStoreP<T>{w.LH, m}, s));
+    SPHX_TRY(vspmm_store<T>(g, w.plan, H, ld, m, EpiStoreP<T>{w.LH, ld}, s));
     pl.end(tid, s);
     ++calls;
-    GramArgs gb{n, m, act, 1, have_p ? 1 : 0, bdiag};
+    GramArgs gb{n, m, ld, act, 1, have_p ? 1 : 0, bdiag};
     tid = pl.begin(PH_GRAM, 0.0, s);
     SPHX_TRY(gram<T>(w.X, w.LX, H, w.LH, w.P, w.LP, gb, w.gram_partials, kGramBlocks,
                      w.gram_out, s));
@@ -379,7 +386,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     launch_rr(w.gram_out, RRArgs{m, wdt, have_p ? m + na : wdt, drop}, w.Y, w.theta,
               w.status, s);
     pl.end(tid, s);
-    UpdateArgs ub{n, m, act, 1, have_p ? 1 : 0};
+    UpdateArgs ub{n, m, ld, act, 1, have_p ? 1 : 0};
     tid = pl.begin(PH_UPDATE, 0.0, s);
     launch_update<T>(w.X, H, w.P, w.LH, w.LP, w.Y, ub, s);
     pl.end(tid, s);
@@ -398,14 +405,14 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   double *X64 = reinterpret_cast<double *>(w.X);
   double *LX64 = reinterpret_cast<double *>(w.LX);
   if constexpr (std::is_same_v<T, float>) {
-    launch_convert<float, double>(w.X, w.X64, n * m, s);
+    launch_convert<float, double>(w.X, w.X64, n * ld, s);
     X64 = w.X64;
     LX64 = w.LX64;
-    SPHX_TRY(spmm_store<double>(g, w.plan, X64, m, idm, EpiStoreP<double>{LX64, m}, s));
+    SPHX_TRY(vspmm_store<double>(g, w.plan, X64, ld, m, EpiStoreP<double>{LX64, ld}, s));
     ++calls;
   }
-  int rb = (int)grid_for(n, 256 / m, kRqBlocks);
-  launch_rq_partials<double>(X64, LX64, n, m, bdiag, w.rq_partials, rb, s);
+  int rb = (int)grid_for(n, 256 / ld, kRqBlocks);
+  launch_rq_partials<double>(X64, LX64, n, m, ld, bdiag, w.rq_partials, rb, s);
   launch_sum_partials(w.rq_partials, rb, m, w.rq_sums, s);
   double sums[2 * kMaxNev];
   SPHX_HIP(h, hipMemcpyAsync(sums, w.rq_sums, sizeof(sums), hipMemcpyDeviceToHost, s));
@@ -413,7 +420,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   double th[kMaxNev];
   for (int c = 0; c < m; ++c) th[c] = sums[kMaxNev + c] > 0 ? sums[c] / sums[kMaxNev + c] : 0;
   SPHX_HIP(h, hipMemcpyAsync(w.theta, th, sizeof(double) * m, hipMemcpyHostToDevice, s));
-  launch_res_partials<double>(X64, LX64, n, m, bdiag, w.theta, w.rq_partials, rb, s);
+  launch_res_partials<double>(X64, LX64, n, m, ld, bdiag, w.theta, w.rq_partials, rb, s);
   launch_sum_partials(w.rq_partials, rb, m, w.res_sums, s);
   double rs[2 * kMaxNev];
   SPHX_HIP(h, hipMemcpyAsync(rs, w.res_sums, sizeof(rs), hipMemcpyDeviceToHost, s));
@@ -437,7 +444,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     scale[q] = rs[kMaxNev + c] > 0 ? 1.0 / std::sqrt(rs[kMaxNev + c]) : 1.0;
   }
   for (int q = 0; q < m; ++q)
-    launch_copy_cols<T>(w.X + perm[q], m, vecs_out + q, m, n, 1, s);
+    launch_copy_cols<T>(w.X + perm[q], ld, vecs_out + q, m, n, 1, s);
   SPHX_TRY(normalize_columns<T>(vecs_out, n, m, scale, w.norm_scratch, s));
   if (stats) {
     stats->iterations = it;
@@ -646,11 +653,18 @@ int sphx_laplacian_apply(sphx_handle *h, sphx_graph *g, int m, int dtype, const 
   SpmmPlan plan;
   SPHX_TRY(build_plan(g, pa, &plan, ds, h->pinned_small, h->stream));
   ColMap cm = identity_map(m);
+  // rows that are whole 16-byte vectors take the vector-row kernels
+  const bool vec = (m * bytes_of(dtype)) % 16 == 0 && ((uintptr_t)X % 16) == 0 &&
+                   ((uintptr_t)Y % 16) == 0;
   if (dtype == SPHX_F32)
-    return spmm_store<float>(g, plan, (const float *)X, m, cm,
-                             EpiStoreP<float>{(float *)Y, m}, h->stream);
-  return spmm_store<double>(g, plan, (const double *)X, m, cm,
-                            EpiStoreP<double>{(double *)Y, m}, h->stream);
+    return vec ? vspmm_store<float>(g, plan, (const float *)X, m, m,
+                                    EpiStoreP<float>{(float *)Y, m}, h->stream)
+               : spmm_store<float>(g, plan, (const float *)X, m, cm,
+                                   EpiStoreP<float>{(float *)Y, m}, h->stream);
+  return vec ? vspmm_store<double>(g, plan, (const double *)X, m, m,
+                                   EpiStoreP<double>{(double *)Y, m}, h->stream)
+             : spmm_store<double>(g, plan, (const double *)X, m, cm,
+                                  EpiStoreP<double>{(double *)Y, m}, h->stream);
 }
 
 int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int m,
@@ -703,12 +717,12 @@ int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int
     h->plog.on = false;
     if (dtype == SPHX_F32) {
       float *res = nullptr;
-      SPHX_TRY(cheb_apply<float>(h, g, plan, m, cm, (const float *)R, (float *)b1,
+      SPHX_TRY(cheb_apply<float>(h, g, plan, m, m, cm, (const float *)R, (float *)b1,
                                  (float *)b2, ck, dv, s, &res, &calls, &pcalls));
       SPHX_HIP(h, hipMemcpyAsync(H, res, blk, hipMemcpyDeviceToDevice, s));
     } else {
       double *res = nullptr;
-      SPHX_TRY(cheb_apply<double>(h, g, plan, m, cm, (const double *)R, (double *)b1,
+      SPHX_TRY(cheb_apply<double>(h, g, plan, m, m, cm, (const double *)R, (double *)b1,
                                   (double *)b2, ck, dv, s, &res, &calls, &pcalls));
       SPHX_HIP(h, hipMemcpyAsync(H, res, blk, hipMemcpyDeviceToDevice, s));
     }
@@ -862,7 +876,7 @@ int sphx_block_gram(sphx_handle *h, int64_t n, int m, int dtype, const void *X,
   SPHX_TRY(get_workspace(h, need, &ws));
   double *parts = reinterpret_cast<double *>(ws);
   double *out = parts + gram_partial_doubles(kGramBlocks);
-  GramArgs a{n, m, identity_map(m), use_h, use_p, bdiag};
+  GramArgs a{n, m, m, identity_map(m), use_h, use_p, bdiag};
   a.act.count = nact;
   for (int q = 0; q < nact; ++q) {
     if (act[q] < 0 || act[q] >= m) return SPHX_E_INVALID_ARG;

@@ -2,7 +2,8 @@
 // on FP64 matrix cores, Rayleigh-Ritz in one workgroup, the fused block
 // update, the convergence check, and final normalisation.
 //
-// Blocks are row-major n x m (ld = m).  The Rayleigh-Ritz basis is
+// Blocks are row-major n x ld (ld >= m; columns m..ld-1 are padding).  The
+// Rayleigh-Ritz basis is
 // S = [X, H_a, P_a] where a lists the active (unconverged) columns.
 #include <cmath>
 
@@ -21,12 +22,20 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+// Element (i, c) draws from the counter i * m + c, independent of the padding.
 template <typename T>
-__global__ void k_init_random(T *X, int64_t count, uint64_t seed) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+__global__ void k_init_random(T *X, int64_t n, int m, int ld, uint64_t seed) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * ld;
        e += (int64_t)gridDim.x * blockDim.x) {
-    uint64_t a = splitmix64(seed ^ splitmix64(2 * (uint64_t)e));
-    uint64_t b = splitmix64(seed ^ splitmix64(2 * (uint64_t)e + 1));
+    const int64_t i = e / ld;
+    const int c = (int)(e - i * ld);
+    if (c >= m) {
+      X[e] = T(0);
+      continue;
+    }
+    const uint64_t ctr = (uint64_t)(i * m + c);
+    uint64_t a = splitmix64(seed ^ splitmix64(2 * ctr));
+    uint64_t b = splitmix64(seed ^ splitmix64(2 * ctr + 1));
     double u1 = (double)((a >> 11) + 1) * 0x1.0p-53;   // (0, 1]
     double u2 = (double)(b >> 11) * 0x1.0p-53;         // [0, 1)
     X[e] = T(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
@@ -36,14 +45,14 @@ __global__ void k_init_random(T *X, int64_t count, uint64_t seed) {
 // Sec. 6.2.1: column 0 is the constant vector; column j >= 1 is the indicator
 // of index block j-1 of d blocks [floor(b n / d), floor((b+1) n / d)).
 template <typename T>
-__global__ void k_init_piecewise(T *X, int64_t n, int m) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * m;
+__global__ void k_init_piecewise(T *X, int64_t n, int m, int ld) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * ld;
        e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t i = e / m;
-    int c = (int)(e - i * m);
+    int64_t i = e / ld;
+    int c = (int)(e - i * ld);
     T v = T(0);
     if (c == 0) v = T(1);
-    else {
+    else if (c < m) {
       int64_t b = c - 1;
       int64_t lo = b * n / m, hi = (b + 1) * n / m;
       v = (i >= lo && i < hi) ? T(1) : T(0);
@@ -59,7 +68,7 @@ constexpr int kCh = 64;   // rows per LDS chunk
 
 struct GramDev {
   int64_t n;
-  int m, w;
+  int m, ld, w;
   int offH, offP;           // column offsets of the H and P parts in S
   int use_h, use_p;
   int inv[kMaxNev];         // inverse active map: column -> position or -1
@@ -90,6 +99,7 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, GramSrc<T> src,
   const int lane = t & 63;
   const int wave = t >> 6;
   const int m = a.m;
+  const int ld = a.ld;
   for (int e = t; e < kCh * WP; e += blockDim.x) {
     sS[e] = 0.0;
     sL[e] = 0.0;
@@ -120,8 +130,8 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, GramSrc<T> src,
 #pragma unroll
   for (int r = 0; r < kPre; ++r) {
     int e = t + 256 * r;
-    int row = e / m, c = e - row * m;
-    bool in = e < kCh * m;
+    int row = e / ld, c = e - row * ld;
+    bool in = e < kCh * ld && c < m;
     dst[0][r] = in ? row * WP + c : -1;
     int pos = (in && a.inv[c] >= 0) ? a.inv[c] : -1;
     dst[1][r] = pos >= 0 ? row * WP + offs[1] + pos : -1;
@@ -131,8 +141,8 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, GramSrc<T> src,
   const int64_t re = min(a.n, rb + rows_per_block);
   T st[6][kPre];
   auto fetch = [&](int64_t r0) {
-    const int64_t base = r0 * m;
-    const int64_t lim = (re - r0) * m;   // valid elements of this chunk
+    const int64_t base = r0 * ld;
+    const int64_t lim = (re - r0) * ld;   // valid elements of this chunk
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
 #pragma unroll
@@ -449,30 +459,32 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
 // --------------------------------------------------------------- update
 struct UpdDev {
   int64_t n;
-  int m;
+  int m, ld;
   int na;
   int act[kMaxNev];
   int use_h, use_p;
   int offH, offP;     // rows of Y for the H and P parts
 };
 
+// Rows of all blocks have stride ld; thread t works on column t % ld of row
+// t / ld of a 256 / ld row chunk staged in LDS (padding columns untouched).
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(T *X, const T *__restrict__ H, T *P,
                                                 const T *__restrict__ LH, T *LP,
                                                 const double *__restrict__ Yg, UpdDev a) {
   __shared__ double sY[kMaxW * kMaxNev];
   __shared__ double sX[256], sH[256], sP[256], sLH[256], sLP[256];
-  const int m = a.m;
-  const int rc = 256 / m;       // rows per chunk
+  const int m = a.m, ld = a.ld;
+  const int rc = 256 / ld;      // rows per chunk
   const int t = threadIdx.x;
   for (int e = t; e < kMaxW * kMaxNev; e += blockDim.x) sY[e] = Yg[e];
-  const int row = t / m;
-  const int c = t - row * m;
-  const bool live = row < rc;
+  const int row = t / ld;
+  const int c = t - row * ld;
+  const bool live = row < rc && c < m;
   const bool write_p = a.use_h || a.use_p;
   for (int64_t r0 = (int64_t)blockIdx.x * rc; r0 < a.n; r0 += (int64_t)gridDim.x * rc) {
-    const int64_t base = r0 * m;
-    const int64_t lim = min((int64_t)rc, a.n - r0) * m;
+    const int64_t base = r0 * ld;
+    const int64_t lim = min((int64_t)rc, a.n - r0) * ld;
     __syncthreads();
     if (t < lim) {
       sX[t] = double(X[base + t]);
@@ -482,7 +494,7 @@ __global__ __launch_bounds__(256) void k_update(T *X, const T *__restrict__ H, T
     __syncthreads();
     if (live && t < lim) {
       double p = 0.0, lp = 0.0, x = 0.0;
-      const int o = row * m;
+      const int o = row * ld;
       if (a.use_h)
         for (int q = 0; q < a.na; ++q) {
           double y = sY[(a.offH + q) * kMaxNev + c];
@@ -582,20 +594,21 @@ __device__ void colsum2(int c, double v1, double v2, int m, double *partials) {
   }
 }
 
-// Rayleigh quotient partials: sum x.lx and sum b x^2 per column.
+// Rayleigh quotient partials: sum x.lx and sum b x^2 per column (blocks of
+// row stride ld; thread t takes column t % ld of rows t / ld).
 template <typename T>
 __global__ __launch_bounds__(256) void k_rq(const T *X, const double *LX, int64_t n, int m,
-                                            const double *bdiag, double *partials) {
-  const int rc = 256 / m;
-  const int row = threadIdx.x / m;
-  const int c = threadIdx.x % m;
-  const bool live = threadIdx.x < rc * m;
+                                            int ld, const double *bdiag, double *partials) {
+  const int rc = 256 / ld;
+  const int row = threadIdx.x / ld;
+  const int c = threadIdx.x % ld;
+  const bool live = threadIdx.x < rc * ld && c < m;
   double a = 0.0, b = 0.0;
   if (live)
     for (int64_t r = (int64_t)blockIdx.x * rc + row; r < n; r += (int64_t)gridDim.x * rc) {
-      double x = double(X[r * m + c]);
+      double x = double(X[r * ld + c]);
       double bd = bdiag ? bdiag[r] : 1.0;
-      a += x * LX[r * m + c];
+      a += x * LX[r * ld + c];
       b += bd * x * x;
     }
   colsum2(live ? c : -1, a, b, m, partials);
@@ -604,19 +617,19 @@ __global__ __launch_bounds__(256) void k_rq(const T *X, const double *LX, int64_
 // Residual partials: sum (lx - theta b x)^2 / b and sum b x^2 per column.
 template <typename T>
 __global__ __launch_bounds__(256) void k_res(const T *X, const double *LX, int64_t n, int m,
-                                             const double *bdiag, const double *theta,
+                                             int ld, const double *bdiag, const double *theta,
                                              double *partials) {
-  const int rc = 256 / m;
-  const int row = threadIdx.x / m;
-  const int c = threadIdx.x % m;
-  const bool live = threadIdx.x < rc * m;
+  const int rc = 256 / ld;
+  const int row = threadIdx.x / ld;
+  const int c = threadIdx.x % ld;
+  const bool live = threadIdx.x < rc * ld && c < m;
   double a = 0.0, b = 0.0;
   if (live) {
     double th = theta[c];
     for (int64_t r = (int64_t)blockIdx.x * rc + row; r < n; r += (int64_t)gridDim.x * rc) {
-      double x = double(X[r * m + c]);
+      double x = double(X[r * ld + c]);
       double bd = bdiag ? bdiag[r] : 1.0;
-      double res = LX[r * m + c] - th * bd * x;
+      double res = LX[r * ld + c] - th * bd * x;
       a += res * res / bd;
       b += bd * x * x;
     }
@@ -705,14 +718,14 @@ __global__ void k_copy_cols(const T *in, int ldin, T *out, int ldout, int64_t n,
 
 // ------------------------------------------------------------ launchers
 template <typename T>
-void launch_init_random(T *X, int64_t n, int m, uint64_t seed, hipStream_t s) {
-  hipLaunchKernelGGL((k_init_random<T>), dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s,
-                     X, n * m, seed);
+void launch_init_random(T *X, int64_t n, int m, int ld, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL((k_init_random<T>), dim3(grid_for(n * ld, 256, 4096)), dim3(256), 0, s,
+                     X, n, m, ld, seed);
 }
 template <typename T>
-void launch_init_piecewise(T *X, int64_t n, int m, hipStream_t s) {
-  hipLaunchKernelGGL((k_init_piecewise<T>), dim3(grid_for(n * m, 256, 4096)), dim3(256), 0,
-                     s, X, n, m);
+void launch_init_piecewise(T *X, int64_t n, int m, int ld, hipStream_t s) {
+  hipLaunchKernelGGL((k_init_piecewise<T>), dim3(grid_for(n * ld, 256, 4096)), dim3(256), 0,
+                     s, X, n, m, ld);
 }
 
 size_t gram_partial_doubles(int max_blocks) {
@@ -726,6 +739,7 @@ int gram(const T *X, const T *LX, const T *H, const T *LH, const T *P, const T *
   GramDev d;
   d.n = a.n;
   d.m = a.m;
+  d.ld = a.ld;
   int na = a.act.count;
   d.use_h = a.use_h && na > 0;
   d.use_p = a.use_p && na > 0;
@@ -774,13 +788,14 @@ void launch_update(T *X, const T *H, T *P, const T *LH, T *LP, const double *Y,
   UpdDev d;
   d.n = a.n;
   d.m = a.m;
+  d.ld = a.ld;
   d.na = a.act.count;
   for (int q = 0; q < kMaxNev; ++q) d.act[q] = q < d.na ? a.act.col[q] : 0;
   d.use_h = a.use_h && d.na > 0;
   d.use_p = a.use_p && d.na > 0;
   d.offH = a.m;
   d.offP = a.m + (d.use_h ? d.na : 0);
-  int rc = 256 / a.m;
+  int rc = 256 / a.ld;
   hipLaunchKernelGGL((k_update<T>), dim3(grid_for(a.n, rc, 8192)), dim3(256), 0, s, X, H, P,
                      LH, LP, Y, d);
 }
@@ -792,14 +807,16 @@ void launch_finalize(const double *norm_partials, int n_blocks, int m, const dou
 }
 
 template <typename T>
-void launch_rq_partials(const T *X, const double *LX, int64_t n, int m, const double *bdiag,
-                        double *partials, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_rq<T>), dim3(nblocks), dim3(256), 0, s, X, LX, n, m, bdiag, partials);
+void launch_rq_partials(const T *X, const double *LX, int64_t n, int m, int ld,
+                        const double *bdiag, double *partials, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_rq<T>), dim3(nblocks), dim3(256), 0, s, X, LX, n, m, ld, bdiag,
+                     partials);
 }
 template <typename T>
-void launch_res_partials(const T *X, const double *LX, int64_t n, int m, const double *bdiag,
-                         const double *theta, double *partials, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_res<T>), dim3(nblocks), dim3(256), 0, s, X, LX, n, m, bdiag, theta,
+void launch_res_partials(const T *X, const double *LX, int64_t n, int m, int ld,
+                         const double *bdiag, const double *theta, double *partials,
+                         int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_res<T>), dim3(nblocks), dim3(256), 0, s, X, LX, n, m, ld, bdiag, theta,
                      partials);
 }
 void launch_sum_partials(const double *partials, int nblocks, int cols, double *out,
@@ -842,15 +859,15 @@ void launch_copy_cols(const T *in, int ldin, T *out, int ldout, int64_t n, int m
 }
 
 #define SPHX_INST(T)                                                                        \
-  template void launch_init_random<T>(T *, int64_t, int, uint64_t, hipStream_t);           \
-  template void launch_init_piecewise<T>(T *, int64_t, int, hipStream_t);                  \
+  template void launch_init_random<T>(T *, int64_t, int, int, uint64_t, hipStream_t);      \
+  template void launch_init_piecewise<T>(T *, int64_t, int, int, hipStream_t);             \
   template int gram<T>(const T *, const T *, const T *, const T *, const T *, const T *,   \
                        const GramArgs &, double *, int, double *, hipStream_t);            \
   template void launch_update<T>(T *, const T *, T *, const T *, T *, const double *,      \
                                  const UpdateArgs &, hipStream_t);                         \
-  template void launch_rq_partials<T>(const T *, const double *, int64_t, int,             \
+  template void launch_rq_partials<T>(const T *, const double *, int64_t, int, int,        \
                                       const double *, double *, int, hipStream_t);         \
-  template void launch_res_partials<T>(const T *, const double *, int64_t, int,            \
+  template void launch_res_partials<T>(const T *, const double *, int64_t, int, int,       \
                                        const double *, const double *, double *, int,      \
                                        hipStream_t);                                       \
   template int normalize_columns<T>(T *, int64_t, int, const double *, void *, hipStream_t); \

@@ -71,7 +71,7 @@ struct EpiChebP {
 
 // Norm partials: 2*kMaxNev sums, each over up to kMaxNormBlocks blocks,
 // stored sum-major (sum q of block b at q * kMaxNormBlocks + b).
-constexpr int kMaxNormBlocks = 4096;
+constexpr int kMaxNormBlocks = 10240;
 // Rayleigh-quotient partials: up to kRqStride blocks, sum-major.
 constexpr int kRqStride = 256;
 
@@ -86,18 +86,34 @@ template <typename T>
 int spmm_cheb(sphx_graph *g, const SpmmPlan &plan, const T *X, int ldx,
               const ColMap &cm, EpiChebP<T> epi, hipStream_t s);
 
+// Padded blocks: n x ld with ld * sizeof(T) a multiple of 16 bytes (columns
+// m..ld-1 are padding).  Thread-per-row products with 16-byte vector loads.
+int padded_ld(int m, int elem_bytes);
+template <typename T>
+int vspmm_store(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
+                EpiStoreP<T> epi, hipStream_t s);
+template <typename T>
+int vspmm_residual(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
+                   EpiResidualP<T> epi, double *norm_partials, int *n_norm_blocks,
+                   hipStream_t s);
+template <typename T>
+int vspmm_cheb(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
+               EpiChebP<T> epi, hipStream_t s);
+
 // ------------------------------------------------------------------ dense
+// Initial blocks (n x ld, columns >= m zero).
 template <typename T>
-void launch_init_random(T *X, int64_t n, int m, uint64_t seed, hipStream_t s);
+void launch_init_random(T *X, int64_t n, int m, int ld, uint64_t seed, hipStream_t s);
 template <typename T>
-void launch_init_piecewise(T *X, int64_t n, int m, hipStream_t s);
+void launch_init_piecewise(T *X, int64_t n, int m, int ld, hipStream_t s);
 
 // Gram matrices of S = [X(all m), H(act), P(act, if have_p)] against
 // LS = [LX, LH, LP] and B S.  Output: reduced upper-tile entries in
 // gram_out[2][kMaxW][kMaxW] (A then B), row-major, only i <= j meaningful.
 struct GramArgs {
   int64_t n;
-  int m;               // X width (= ld of every block)
+  int m;               // X width
+  int ld;              // row stride of every block (>= m)
   ColMap act;          // active columns for H and P
   int use_h, use_p;
   const double *bdiag; // nullable: B = I
@@ -125,6 +141,7 @@ void launch_rr(const double *gram_out, const RRArgs &a, double *Y, double *theta
 struct UpdateArgs {
   int64_t n;
   int m;
+  int ld;              // row stride of every block (>= m)
   ColMap act;
   int use_h, use_p;
 };
@@ -139,11 +156,11 @@ void launch_finalize(const double *norm_partials, int n_blocks, int m,
 
 // Rayleigh quotients / residual norms in FP64 of a final block.
 template <typename T>
-void launch_rq_partials(const T *X, const double *LX, int64_t n, int m,
+void launch_rq_partials(const T *X, const double *LX, int64_t n, int m, int ld,
                         const double *bdiag, double *partials, int nblocks,
                         hipStream_t s);
 template <typename T>
-void launch_res_partials(const T *X, const double *LX, int64_t n, int m,
+void launch_res_partials(const T *X, const double *LX, int64_t n, int m, int ld,
                          const double *bdiag, const double *theta,
                          double *partials, int nblocks, hipStream_t s);
 // Sum partials[nblocks][2*kMaxNev] into out[2*kMaxNev] (fixed order).

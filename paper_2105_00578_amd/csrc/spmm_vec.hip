@@ -1,0 +1,466 @@
+// Laplacian block product Y = L_C X over padded row-major blocks (Eq. 2 with
+// weights, difference form y_i = sum_j w_ij (x_i - x_j)).
+//
+// The LOBPCG blocks are n x ld with ld * sizeof(T) a multiple of 16 bytes,
+// so a row is NV = ld * sizeof(T) / 16 aligned 16-byte vectors.  Short rows
+// are handled one thread per row: the thread keeps x_i and the NV-vector
+// accumulator in registers and gathers each neighbour row with NV vector
+// loads (adjacent threads take adjacent rows, so on mesh-like graphs the
+// gathers of a wavefront are contiguous).  Blocks of rows are mapped so that
+// each of the 8 XCDs (hardware places consecutive workgroups round robin on
+// them) works on one contiguous eighth of the rows, which keeps the gathered
+// neighbours of a mesh in that XCD's L2.  Mid-degree rows use a wavefront
+// per row (lanes over the neighbours, butterfly reduction in a fixed order),
+// hub rows fixed-size chunks combined in a second pass.  All sums are in a
+// fixed order, so results are bitwise reproducible.
+//
+// Epilogues (whole rows): Store, Residual (r = acc - b_i theta_c x_i, output r
+// or the Jacobi step r / d_i, FP64 norm partials of ||r||^2_{B^-1} and
+// ||x||^2_B per column c < m), and one Chebyshev step of the iteration for
+// L h = r (Sec. 5.2).
+#include "kernels.h"
+
+namespace sphx {
+namespace {
+
+template <typename T> struct Vec;
+template <> struct Vec<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int E = 4;
+};
+template <> struct Vec<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int E = 2;
+};
+
+template <typename IdxT, typename WT>
+struct Csr {
+  const IdxT *rp;
+  const int32_t *col;
+  const WT *w;
+};
+
+// Block id remap: XCD x = b % 8 receives a contiguous range of block ids.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+  const int64_t q = nb / 8, r = nb % 8;
+  const int64_t x = b % 8, pos = b / 8;
+  return x * q + (x < r ? x : r) + pos;
+}
+
+template <typename T, int NV, typename IdxT, typename WT>
+__device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t k0, int64_t k1,
+                                         int step, const typename Vec<T>::type *__restrict__ X,
+                                         int ldv, const typename Vec<T>::type (&xi)[NV],
+                                         typename Vec<T>::type (&acc)[NV]) {
+  using V = typename Vec<T>::type;
+  V a0[NV], a1[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) { a0[v] = V(0); a1[v] = V(0); }
+  int64_t k = k0;
+  for (; k + step < k1; k += 2 * step) {
+    const int64_t j0 = A.col[k], j1 = A.col[k + step];
+    V x0[NV], x1[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      x0[v] = X[j0 * ldv + v];
+      x1[v] = X[j1 * ldv + v];
+    }
+    if constexpr (std::is_same_v<WT, Unit>) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        a0[v] += xi[v] - x0[v];
+        a1[v] += xi[v] - x1[v];
+      }
+    } else {
+      const T w0 = T(A.w[k]), w1 = T(A.w[k + step]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        a0[v] += w0 * (xi[v] - x0[v]);
+        a1[v] += w1 * (xi[v] - x1[v]);
+      }
+    }
+  }
+  if (k < k1) {
+    const int64_t j0 = A.col[k];
+    if constexpr (std::is_same_v<WT, Unit>) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a0[v] += xi[v] - X[j0 * ldv + v];
+    } else {
+      const T w0 = T(A.w[k]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a0[v] += w0 * (xi[v] - X[j0 * ldv + v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = a0[v] + a1[v];
+}
+
+// ------------------------------------------------------------- epilogues
+template <typename T, int NV>
+struct VStore {
+  EpiStoreP<T> p;
+  static constexpr bool kNorms = false;
+  using V = typename Vec<T>::type;
+  __device__ void row(int64_t i, const V (&xi)[NV], const V (&acc)[NV], double *, double *) const {
+    V *y = reinterpret_cast<V *>(p.Y + i * p.ldy);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) y[v] = acc[v];
+  }
+};
+
+template <typename T, int NV>
+struct VResidual {
+  EpiResidualP<T> p;
+  int m;
+  static constexpr bool kNorms = true;
+  using V = typename Vec<T>::type;
+  static constexpr int E = Vec<T>::E;
+  __device__ void row(int64_t i, const V (&xi)[NV], const V (&acc)[NV], double *n1,
+                      double *n2) const {
+    const double di = p.d64 ? p.d64[i] : 1.0;
+    const double b = p.generalized ? di : 1.0;
+    V *lx = reinterpret_cast<V *>(p.LX + i * p.ld);
+    V *out = reinterpret_cast<V *>(p.OUT + i * p.ld);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      V o;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int c = v * E + e;
+        const double x = double(xi[v][e]);
+        const double th = c < m ? p.theta[c] : 0.0;
+        const double r = double(acc[v][e]) - b * th * x;
+        o[e] = T(p.jacobi ? r / di : r);
+        if (c < m) {
+          n1[c] += r * r / b;
+          n2[c] += b * x * x;
+        }
+      }
+      lx[v] = acc[v];
+      out[v] = o;
+    }
+  }
+};
+
+template <typename T, int NV>
+struct VCheb {
+  EpiChebP<T> p;
+  static constexpr bool kNorms = false;
+  using V = typename Vec<T>::type;
+  static constexpr int E = Vec<T>::E;
+  __device__ void row(int64_t i, const V (&xi)[NV], const V (&acc)[NV], double *, double *) const {
+    const double si = p.dinv ? p.dinv[i] : 1.0;
+    const V *rr = reinterpret_cast<const V *>(p.R + i * p.ld);
+    const V *pp = p.prev ? reinterpret_cast<const V *>(p.prev + i * p.ld) : nullptr;
+    V *out = reinterpret_cast<V *>(p.OUT + i * p.ld);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const V r = rr[v];
+      const V pv = pp ? pp[v] : V(0);
+      V o;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const double xs = p.src_scale * double(xi[v][e]);
+        const double pr = p.prev_scale * double(pv[e]);
+        const double res = double(r[e]) - p.src_scale * double(acc[v][e]);
+        o[e] = T(xs + p.alpha * (xs - pr) + p.beta * si * res);
+      }
+      out[v] = o;
+    }
+  }
+};
+
+// Per-column block sums of the thread norms (columns < m), fixed order:
+// butterfly within each wavefront, then the 4 wavefronts in order.
+template <int LD>
+__device__ void block_norms(const double (&n1)[LD], const double (&n2)[LD], int m,
+                            double *partials, int slot) {
+  __shared__ double sh[4][2 * kMaxNev];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < LD; ++c) {
+    if (c >= m) break;
+    double a = n1[c], b = n2[c];
+    for (int off = 32; off >= 1; off >>= 1) {
+      a += __shfl_xor(a, off);
+      b += __shfl_xor(b, off);
+    }
+    if (lane == 0) {
+      sh[wave][c] = a;
+      sh[wave][kMaxNev + c] = b;
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < m) {
+    double a = sh[0][t] + sh[1][t] + sh[2][t] + sh[3][t];
+    double b = sh[0][kMaxNev + t] + sh[1][kMaxNev + t] + sh[2][kMaxNev + t] +
+               sh[3][kMaxNev + t];
+    partials[(int64_t)t * kMaxNormBlocks + slot] = a;
+    partials[(int64_t)(kMaxNev + t) * kMaxNormBlocks + slot] = b;
+  }
+}
+
+// ----------------------------------------------------------------- kernels
+// Short rows, one thread per row; `rpt` rows per thread, 256-row strides.
+template <typename T, int NV, typename IdxT, typename WT, typename Epi>
+__global__ __launch_bounds__(256) void k_vrow(Csr<IdxT, WT> A, const int32_t *__restrict__ rows,
+                                              int64_t nrows, const T *__restrict__ Xs, int ld,
+                                              int rpt, Epi epi, double *partials, int slot0,
+                                              int m) {
+  using V = typename Vec<T>::type;
+  constexpr int LD = NV * Vec<T>::E;
+  const V *X = reinterpret_cast<const V *>(Xs);
+  const int ldv = ld / Vec<T>::E;
+  const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+  double n1[LD], n2[LD];
+#pragma unroll
+  for (int c = 0; c < LD; ++c) { n1[c] = 0.0; n2[c] = 0.0; }
+  for (int q = 0; q < rpt; ++q) {
+    const int64_t r = (b * rpt + q) * 256 + threadIdx.x;
+    if (r >= nrows) break;
+    const int64_t i = rows ? rows[r] : r;
+    V xi[NV], acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
+    vrow_acc<T, NV>(A, (int64_t)A.rp[i], (int64_t)A.rp[i + 1], 1, X, ldv, xi, acc);
+    epi.row(i, xi, acc, n1, n2);
+  }
+  if constexpr (Epi::kNorms) block_norms<LD>(n1, n2, m, partials, slot0 + (int)blockIdx.x);
+}
+
+template <typename T, int NV>
+__device__ __forceinline__ void wave_sum(typename Vec<T>::type (&acc)[NV]) {
+  constexpr int E = Vec<T>::E;
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      T a = acc[v][e];
+      for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off);
+      acc[v][e] = a;
+    }
+}
+
+// Mid rows: one wavefront per row.
+template <typename T, int NV, typename IdxT, typename WT, typename Epi>
+__global__ __launch_bounds__(256) void k_vrow_wave(Csr<IdxT, WT> A,
+                                                   const int32_t *__restrict__ rows,
+                                                   int64_t nrows, const T *__restrict__ Xs,
+                                                   int ld, Epi epi, double *partials, int slot0,
+                                                   int m) {
+  using V = typename Vec<T>::type;
+  constexpr int LD = NV * Vec<T>::E;
+  const V *X = reinterpret_cast<const V *>(Xs);
+  const int ldv = ld / Vec<T>::E;
+  const int lane = threadIdx.x & 63;
+  double n1[LD], n2[LD];
+#pragma unroll
+  for (int c = 0; c < LD; ++c) { n1[c] = 0.0; n2[c] = 0.0; }
+  for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < nrows;
+       r += (int64_t)gridDim.x * 4) {
+    const int64_t i = rows[r];
+    V xi[NV], acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
+    vrow_acc<T, NV>(A, (int64_t)A.rp[i] + lane, (int64_t)A.rp[i + 1], 64, X, ldv, xi, acc);
+    wave_sum<T, NV>(acc);
+    if (lane == 0) epi.row(i, xi, acc, n1, n2);
+  }
+  if constexpr (Epi::kNorms) block_norms<LD>(n1, n2, m, partials, slot0 + (int)blockIdx.x);
+}
+
+// Hub rows, pass 1: one wavefront per chunk -> partial row sums (as double).
+template <typename T, int NV, typename IdxT, typename WT>
+__global__ __launch_bounds__(256) void k_vhub_partial(
+    Csr<IdxT, WT> A, const int32_t *__restrict__ hub_rows,
+    const int32_t *__restrict__ hub_chunk_begin, int64_t n_hub,
+    const int64_t *__restrict__ k0s, const int64_t *__restrict__ k1s, int64_t n_chunks,
+    const T *__restrict__ Xs, int ld, double *out) {
+  using V = typename Vec<T>::type;
+  constexpr int E = Vec<T>::E;
+  const V *X = reinterpret_cast<const V *>(Xs);
+  const int ldv = ld / E;
+  const int lane = threadIdx.x & 63;
+  for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < n_chunks;
+       q += (int64_t)gridDim.x * 4) {
+    int64_t lo = 0, hi = n_hub - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) / 2;
+      if (hub_chunk_begin[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    const int64_t i = hub_rows[lo];
+    V xi[NV], acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
+    vrow_acc<T, NV>(A, k0s[q] + lane, k1s[q], 64, X, ldv, xi, acc);
+    wave_sum<T, NV>(acc);
+    if (lane == 0)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < E; ++e) out[q * kMaxNev + v * E + e] = double(acc[v][e]);
+  }
+}
+
+// Hub rows, pass 2: one thread per hub row sums its chunks in order.
+template <typename T, int NV, typename Epi>
+__global__ __launch_bounds__(256) void k_vhub_combine(const int32_t *__restrict__ hub_rows,
+                                                      const int32_t *__restrict__ hub_chunk_begin,
+                                                      int64_t n_hub, const double *part,
+                                                      const T *__restrict__ Xs, int ld, Epi epi,
+                                                      double *partials, int slot0, int m) {
+  using V = typename Vec<T>::type;
+  constexpr int E = Vec<T>::E;
+  constexpr int LD = NV * E;
+  const V *X = reinterpret_cast<const V *>(Xs);
+  const int ldv = ld / E;
+  double n1[LD], n2[LD];
+#pragma unroll
+  for (int c = 0; c < LD; ++c) { n1[c] = 0.0; n2[c] = 0.0; }
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_hub;
+       h += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = hub_rows[h];
+    V xi[NV], acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      xi[v] = X[i * ldv + v];
+      acc[v] = V(0);
+    }
+    for (int64_t q = hub_chunk_begin[h]; q < hub_chunk_begin[h + 1]; ++q)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[v][e] += T(part[q * kMaxNev + v * E + e]);
+    epi.row(i, xi, acc, n1, n2);
+  }
+  if constexpr (Epi::kNorms) block_norms<LD>(n1, n2, m, partials, slot0 + (int)blockIdx.x);
+}
+
+// ----------------------------------------------------------------- dispatch
+constexpr int kMaxShortBlocks = 8192;
+constexpr int kWaveBlocks = 1024;
+constexpr int kHubBlocks = 16;
+
+template <typename T, int NV, typename IdxT, typename WT, typename Epi>
+void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X, int ld,
+             const Epi &epi, double *partials, int *nparts, int m, hipStream_t s) {
+  int used = 0;
+  auto short_rows = [&](const int32_t *rows, int64_t nr) {
+    int64_t nb = ceil_div(nr, 256);
+    int rpt = (int)ceil_div(nb, kMaxShortBlocks);
+    nb = ceil_div(nr, 256 * (int64_t)rpt);
+    hipLaunchKernelGGL((k_vrow<T, NV, IdxT, WT, Epi>), dim3((unsigned)nb), dim3(256), 0, s, A,
+                       rows, nr, X, ld, rpt, epi, partials, used, m);
+    used += (int)nb;
+  };
+  if (!plan.binned) {
+    short_rows(nullptr, n);
+  } else {
+    if (plan.n_short > 0) short_rows(plan.short_rows, plan.n_short);
+    if (plan.n_mid > 0) {
+      unsigned gb = grid_for(plan.n_mid, 4, kWaveBlocks);
+      hipLaunchKernelGGL((k_vrow_wave<T, NV, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s, A,
+                         plan.mid_rows, plan.n_mid, X, ld, epi, partials, used, m);
+      used += (int)gb;
+    }
+    if (plan.n_hub > 0) {
+      unsigned gb = grid_for(plan.n_chunks, 4, kWaveBlocks);
+      hipLaunchKernelGGL((k_vhub_partial<T, NV, IdxT, WT>), dim3(gb), dim3(256), 0, s, A,
+                         plan.hub_rows, plan.hub_chunk_begin, plan.n_hub, plan.chunk_k0,
+                         plan.chunk_k1, plan.n_chunks, X, ld, plan.hub_partial);
+      unsigned gc = grid_for(plan.n_hub, 256, kHubBlocks);
+      hipLaunchKernelGGL((k_vhub_combine<T, NV, Epi>), dim3(gc), dim3(256), 0, s,
+                         plan.hub_rows, plan.hub_chunk_begin, plan.n_hub,
+                         (const double *)plan.hub_partial, X, ld, epi, partials, used, m);
+      used += (int)gc;
+    }
+  }
+  if (nparts) *nparts = used;
+}
+
+template <typename T, int NV, template <typename, int> class EpiT, typename P>
+int dispatch_types(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, const P &p,
+                   int m, double *partials, int *nparts, hipStream_t s) {
+  auto go = [&](auto idx_tag, auto w_tag) {
+    using IdxT = decltype(idx_tag);
+    using WT = decltype(w_tag);
+    Csr<IdxT, WT> A{static_cast<const IdxT *>(g->rowptr), g->col,
+                    static_cast<const WT *>(g->w)};
+    EpiT<T, NV> epi{p};
+    if constexpr (std::is_same_v<EpiT<T, NV>, VResidual<T, NV>>) epi.m = m;
+    run_vec<T, NV>(A, g->n, plan, X, ld, epi, partials, nparts, m, s);
+  };
+  if (g->rp64) {
+    if (g->wdt == SPHX_UNIT) go(int64_t{}, Unit{});
+    else if (g->wdt == SPHX_F32) go(int64_t{}, float{});
+    else go(int64_t{}, double{});
+  } else {
+    if (g->wdt == SPHX_UNIT) go(int32_t{}, Unit{});
+    else if (g->wdt == SPHX_F32) go(int32_t{}, float{});
+    else go(int32_t{}, double{});
+  }
+  return hipGetLastError() == hipSuccess ? SPHX_OK : SPHX_E_HIP;
+}
+
+template <typename T, template <typename, int> class EpiT, typename P>
+int dispatch_nv(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, const P &p, int m,
+                double *partials, int *nparts, hipStream_t s) {
+  constexpr int E = Vec<T>::E;
+  if (ld % E != 0 || ld < m || ld > kMaxNev || m < 1) return SPHX_E_INVALID_ARG;
+  const int nv = ld / E;
+  switch (nv) {
+    case 1: return dispatch_types<T, 1, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
+    case 2: return dispatch_types<T, 2, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
+    case 3: return dispatch_types<T, 3, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
+    case 4: return dispatch_types<T, 4, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
+    default: break;
+  }
+  if constexpr (E == 2) {
+    switch (nv) {
+      case 5: return dispatch_types<T, 5, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
+      case 6: return dispatch_types<T, 6, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
+      case 7: return dispatch_types<T, 7, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
+      case 8: return dispatch_types<T, 8, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
+      default: break;
+    }
+  }
+  return SPHX_E_INVALID_ARG;
+}
+
+}  // namespace
+
+int padded_ld(int m, int elem_bytes) {
+  const int e = 16 / elem_bytes;
+  return (m + e - 1) / e * e;
+}
+
+template <typename T>
+int vspmm_store(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
+                EpiStoreP<T> epi, hipStream_t s) {
+  return dispatch_nv<T, VStore>(g, plan, X, ld, epi, m, nullptr, nullptr, s);
+}
+template <typename T>
+int vspmm_residual(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
+                   EpiResidualP<T> epi, double *norm_partials, int *n_norm_blocks,
+                   hipStream_t s) {
+  return dispatch_nv<T, VResidual>(g, plan, X, ld, epi, m, norm_partials, n_norm_blocks, s);
+}
+template <typename T>
+int vspmm_cheb(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
+               EpiChebP<T> epi, hipStream_t s) {
+  return dispatch_nv<T, VCheb>(g, plan, X, ld, epi, m, nullptr, nullptr, s);
+}
+
+#define SPHX_VINST(T)                                                                       \
+  template int vspmm_store<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,         \
+                              EpiStoreP<T>, hipStream_t);                                  \
+  template int vspmm_residual<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,      \
+                                 EpiResidualP<T>, double *, int *, hipStream_t);           \
+  template int vspmm_cheb<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,          \
+                             EpiChebP<T>, hipStream_t);
+SPHX_VINST(float)
+SPHX_VINST(double)
+#undef SPHX_VINST
+
+}  // namespace sphx

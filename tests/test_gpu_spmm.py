@@ -53,7 +53,7 @@ def _bound(g, X, eps):
 
 @pytest.mark.parametrize("name", list(GRAPHS))
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-@pytest.mark.parametrize("m", [1, 3, 7, 16])
+@pytest.mark.parametrize("m", [1, 3, 4, 7, 8, 16])
 def test_spmm_matches_oracle(handle, name, dtype, m):
     g = GRAPHS[name]
     rp64 = name in ("rand_f64", "star_hub")

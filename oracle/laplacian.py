@@ -72,6 +72,19 @@ def apply(rowptr, col, w, X):
     return Y[:, 0] if squeeze else Y
 
 
+def apply_sparse(rowptr, col, w, X):
+    """Y = L_C X in FP64 as D X - A X with a library sparse product, for graphs
+    too large for `apply`.  The same operator (Eq. 2 weighted); only the
+    rounding order differs from the difference form."""
+    import scipy.sparse as sp
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    n = rowptr.size - 1
+    A = sp.csr_matrix((_weights(col, w), np.asarray(col, dtype=np.int64), rowptr), shape=(n, n))
+    d = np.asarray(A.sum(axis=1)).ravel()
+    X = np.asarray(X, dtype=np.float64)
+    return (d[:, None] * X if X.ndim == 2 else d * X) - A @ X
+
+
 def dense(rowptr, col, w, n=None):
     """Dense (L_C, d) built entry by entry from Eq. 2: L_ii = d_i, L_ij = -w_ij."""
     rowptr = np.asarray(rowptr, dtype=np.int64)

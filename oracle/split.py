@@ -46,17 +46,20 @@ def split_pow2(coords, K, vwgt=None):
     ids = np.arange(n, dtype=np.int64)
     for level in range(m):
         key = coords[:, level % ncoord].astype(np.float64) + 0.0   # -0 -> +0
+        # all sections at once: order by (section, value, id); lexsort sorts
+        # by the last key first
+        order = np.lexsort((ids, key, part))
+        sec = part[order]
+        starts = np.flatnonzero(np.concatenate([[True], sec[1:] != sec[:-1]]))
+        ends = np.concatenate([starts[1:], [n]])
+        cw = np.cumsum(wts[order])                     # running weight over all
         newpart = part * 2
-        for s in np.unique(part):
-            members = ids[part == s]
-            # order by (value, id): lexsort sorts by the last key first
-            order = members[np.lexsort((members, key[members]))]
-            cw = np.cumsum(wts[order])
-            total = int(cw[-1]) if cw.size else 0
-            # prefix lengths p = 0..c; W_lo(p) = cw[p-1] (0 for p = 0)
-            wlo = np.concatenate([[0], cw])
+        for a, b in zip(starts, ends):
+            base = cw[a - 1] if a > 0 else 0
+            wlo = np.concatenate([[0], cw[a:b] - base])  # W_lo(p), p = 0..c
+            total = int(wlo[-1])
             dev = np.abs(2 * wlo - total)
-            p = int(np.argmin(dev))            # first minimiser = shortest
-            newpart[order[p:]] += 1
+            p = int(np.argmin(dev))                    # first minimiser = shortest
+            newpart[order[a + p:b]] += 1
         part = newpart
     return part.astype(np.int32)

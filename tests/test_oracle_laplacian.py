@@ -44,6 +44,14 @@ def test_apply_matches_entrywise_dense_D_minus_A_and_is_symmetric():
     assert y @ Y[:, 0] == pytest.approx(X[:, 0] @ lap.apply(g.rowptr, g.col, g.w, y), rel=1e-12)
 
 
+def test_sparse_form_matches_difference_form():
+    g, _ = _random_weighted()
+    X = np.random.default_rng(2).standard_normal((g.n, 3))
+    a = lap.apply(g.rowptr, g.col, g.w, X)
+    b = lap.apply_sparse(g.rowptr, g.col, g.w, X)
+    assert np.allclose(a, b, rtol=0, atol=1e-12 * np.abs(X).max() * 10)
+
+
 def test_degrees_bruteforce():
     g, (u, v, w) = _random_weighted()
     d = np.zeros(g.n)

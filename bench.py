@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cheb-ratio", type=float, default=100.0)
+    ap.add_argument("--cheb-ratio", type=float, default=1000.0)
     ap.add_argument("--scale-down", type=int, default=1, help="shrink the grid (tests only)")
     args = ap.parse_args()
     if args.gpus != 1:

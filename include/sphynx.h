@@ -56,8 +56,14 @@ enum {
 /* dtype tags for untyped pointers */
 enum { SPHX_UNIT = 0, SPHX_F32 = 1, SPHX_F64 = 2 };
 
-/* eigenvalue problem (Sec. 3.2): L_C x = lambda x, or L_C x = lambda D x */
-enum { SPHX_COMBINATORIAL = 0, SPHX_GENERALIZED = 1 };
+/* eigenvalue problem (Sec. 3.2): L_C x = lambda x, L_C x = lambda D x, or
+ * L_N y = lambda y with L_N = I - D^-1/2 A D^-1/2 (the normalized Laplacian).
+ * The normalized problem is solved as the generalized one in the variables
+ * x = D^-1/2 y (the same pencil up to the congruence D^1/2, so the same
+ * eigenvalues, LOBPCG iterates and relative residuals in exact arithmetic);
+ * its initial block is given in y and its eigenvectors are returned as
+ * y = D^1/2 x with unit 2-norm.  It needs every weighted degree > 0. */
+enum { SPHX_COMBINATORIAL = 0, SPHX_GENERALIZED = 1, SPHX_NORMALIZED = 2 };
 
 /* preconditioner (Sec. 5): none, Jacobi (Sec. 5.1), Chebyshev polynomial
  * (Sec. 5.2 names a degree-25 polynomial preconditioner) */
@@ -78,15 +84,17 @@ typedef struct sphx_handle sphx_handle;
 typedef struct sphx_graph sphx_graph;
 
 typedef struct sphx_options {
-    int problem;          /* SPHX_COMBINATORIAL / SPHX_GENERALIZED          */
+    int problem;          /* SPHX_COMBINATORIAL / _GENERALIZED / _NORMALIZED */
     int precond;          /* SPHX_PRECOND_*                                  */
     int cheb_degree;      /* SpMMs per Chebyshev apply (default 25)          */
-    double cheb_ratio;    /* Chebyshev interval [hi/ratio, hi]; hi is the
-                             Gershgorin bound (2 max_i d_i, or 2 for D^-1 L) */
+    double cheb_ratio;    /* Chebyshev interval [hi/ratio, hi]; hi bounds the
+                             spectrum: 2 max_i d_i (Gershgorin) for L_C, 2 for
+                             D^-1 L_C and L_N                                */
     int precision;        /* SPHX_FP64 / SPHX_MIXED                          */
     double tol;           /* bound on every relative residual rho_i:
                              ||L x_i - theta_i B x_i||_{B^-1}
-                               / (max(theta_i, theta_1) ||x_i||_B)            */
+                               / (max(theta_i, theta_1) ||x_i||_B)
+                             (B = I for L_N)                                  */
     int max_iter;         /* LOBPCG iterations (default 10000)               */
     int init;             /* SPHX_INIT_*                                      */
     uint64_t seed;        /* for SPHX_INIT_RANDOM                             */
@@ -139,12 +147,11 @@ int sphx_set_timing(sphx_handle *h, int on);
 int sphx_num_eigenvectors(int K);
 
 /* Defaults of Sec. 6.3.1 ("Sphynx Default Settings") for a preconditioner:
- * regular graphs use the combinatorial problem, irregular graphs the
- * generalized one; the tolerance is 1e-3 on regular graphs and 1e-2 on
- * irregular ones; initial vectors are random on regular graphs and piecewise
- * constant on irregular ones (Sec. 6.2.1).  (The paper's normalized-Laplacian
- * choice for irregular graphs with a polynomial preconditioner is not
- * offered; the generalized problem is used instead.) */
+ * regular graphs use the combinatorial problem; irregular graphs the
+ * normalized one with the polynomial (Chebyshev) preconditioner and the
+ * generalized one otherwise; the tolerance is 1e-3 on regular graphs and 1e-2
+ * on irregular ones; initial vectors are random on regular graphs and
+ * piecewise constant on irregular ones (Sec. 6.2.1). */
 void sphx_options_default(sphx_options *opt, int graph_is_regular, int precond);
 
 /* ---------------------------------------------------------------- graphs */
@@ -182,16 +189,23 @@ int sphx_set_workspace(sphx_handle *h, void *dev_ptr, size_t bytes);
 
 /* -------------------------------------------------------------- operators */
 
-/* Y = L_C X (Eq. 2 with weights), X and Y device n x m blocks of dtype
- * SPHX_F32 or SPHX_F64 (1 <= m <= 32).  Summed per row as
- * sum_j w_ij (x_i - x_j), so constant vectors map to exact zeros. */
-int sphx_laplacian_apply(sphx_handle *h, sphx_graph *g, int m, int dtype,
+/* Y = L X for the matrix of `problem`: L_C (Eq. 2 with weights) for the
+ * combinatorial and generalized problems, L_N = D^-1/2 L_C D^-1/2 (the
+ * normalized Laplacian, Sec. 3.2) for SPHX_NORMALIZED.  X and Y are device
+ * n x m row-major blocks of dtype SPHX_F32 or SPHX_F64 (1 <= m <= 16), not
+ * overlapping.  L_C is summed per row as sum_j w_ij (x_i - x_j), so constant
+ * vectors map to exact zeros; L_N scales the rows of X by D^-1/2 (rounded to
+ * dtype), applies L_C and scales the result by D^-1/2, and needs every
+ * weighted degree > 0 (else SPHX_E_INVALID_ARG). */
+int sphx_laplacian_apply(sphx_handle *h, sphx_graph *g, int problem, int m, int dtype,
                          const void *X, void *Y);
 
 /* H = T R for the LOBPCG preconditioner T of `opt` (Sec. 5; Algorithm 1
- * "solve M H = R"): Jacobi h_ic = r_ic / d_i; Chebyshev: cheb_degree steps of
- * the Chebyshev iteration for L h = r (generalized: D^-1 L h = D^-1 r) from
- * h = 0 on [hi/cheb_ratio, hi]; NONE copies.  R, H: device n x m, dtype. */
+ * "solve M H = R"): Jacobi h_ic = r_ic / diag(L)_i (d_i; 1 for L_N, a copy);
+ * Chebyshev: cheb_degree steps of the Chebyshev iteration for L h = r
+ * (generalized: D^-1 L_C h = D^-1 r; normalized: L_N h = r, computed as
+ * D^1/2 p(D^-1 L_C) D^-1 (D^1/2 r)) from h = 0 on [hi/cheb_ratio, hi];
+ * NONE copies.  R, H: device n x m, dtype. */
 int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *opt,
                        int m, int dtype, const void *R, void *H);
 
@@ -256,6 +270,10 @@ int sphx_partition(sphx_handle *h, sphx_graph *g, int K, const sphx_options *opt
  * spectrum enters through mu_k solving (L - lambda_k B) mu_k =
  * g_k - B V V^T g_k with V^T B mu_k = 0 (projected, Jacobi-preconditioned
  * conjugate gradients to relative residual cg_tol, at most cg_max_iter).
+ * For SPHX_NORMALIZED (eigvecs y = D^1/2 x of unit 2-norm) the gradient is
+ * the generalized one for x with dl/dx = D^1/2 dl/dy, plus, on each edge
+ * {i, j}, t_i + t_j with t_i = sum_k (dl/dy_ik) y_ik / (2 d_i) from the
+ * dependence of D^1/2 on w.
  * The graph must carry F64 weights or unit weights.
  * Returns SPHX_NOT_CONVERGED if a CG solve stopped at cg_max_iter. */
 int sphx_eig_backward(sphx_handle *h, sphx_graph *g, int problem, int nev,

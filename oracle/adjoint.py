@@ -13,9 +13,11 @@ B-orthonormal eigenvectors of L v = lambda B v with simple eigenvalues,
 l(lambda, V) with partials g_lambda (per eigenvalue) and g_k = dl/dv_k, the
 edge gradient is dl/dw_e = sum_k g_lambda_k dlambda_k/dw_e + g_k^T dv_k/dw_e.
 
-Two evaluations:
+Three evaluations:
   grad_dense      - the formula above with the full eigenbasis of a dense
                     pencil (tiny graphs);
+  grad_dense_normalized - the same for L_N y = lambda y (B = I), with dL_N
+                    written out densely per edge;
   grad_projected  - only the computed block V (eigenpairs 0..nev-1) is used;
                     the sum over eigenvectors outside the block is replaced by
                     mu_k, the solution of (L - lambda_k B) mu_k = g_k - B V V^T g_k
@@ -73,6 +75,58 @@ def grad_dense(rowptr, col, w, problem, nev, g_lam, g_V):
         if gen:
             grad += -0.5 * (gk @ vk) * (vk[r] ** 2 + vk[c] ** 2)
     return grad, lam[:nev], V[:, :nev]
+
+
+def dLN_dense(rowptr, col, w, a, b):
+    """d L_N / d w_e for the edge e = {a, b} as a dense matrix, from
+    L_N = I - S A S with S = D^-1/2: raising w_e by dw adds dw to A_ab and
+    A_ba and to d_a and d_b, so dS = -1/2 D^-3/2 dD and
+    dL_N = -(dS A S + S dA S + S A dS)."""
+    L, d = laplacian.dense(rowptr, col, w)
+    n = d.size
+    A = np.diag(d) - L
+    S = np.diag(1.0 / np.sqrt(d))
+    dA = np.zeros((n, n))
+    dA[a, b] = dA[b, a] = 1.0
+    dd = np.zeros(n)
+    dd[a] = dd[b] = 1.0
+    dS = np.diag(-0.5 * d ** -1.5 * dd)
+    return -(dS @ A @ S + S @ dA @ S + S @ A @ dS)
+
+
+def grad_dense_normalized(rowptr, col, w, nev, g_lam, g_V):
+    """Full-eigenbasis edge gradient for the normalized problem L_N y = lambda y
+    (standard symmetric: d lambda_k = y_k^T dL_N y_k and
+    d y_k = sum_{j != k} y_j (y_j^T dL_N y_k) / (lambda_k - lambda_j)), with
+    dL_N formed densely for every edge (tiny graphs).  Returns
+    (grad per CSR entry, lam[:nev], Y[:, :nev])."""
+    LN = laplacian.dense_normalized(rowptr, col, w)
+    n = LN.shape[0]
+    lam, Y = eigen.all_dense(LN, np.ones(n))
+    Y = eigen.normalize_signs(Y)
+    g_lam = np.zeros(nev) if g_lam is None else np.asarray(g_lam, float)
+    g_V = np.zeros((n, nev)) if g_V is None else np.asarray(g_V, float)
+    r = laplacian.row_index(rowptr)
+    c = np.asarray(col, dtype=np.int64)
+    grad = np.zeros(r.size)
+    cache = {}
+    for q in range(r.size):
+        a, b = int(min(r[q], c[q])), int(max(r[q], c[q]))
+        if (a, b) not in cache:
+            dL = dLN_dense(rowptr, col, w, a, b)
+            P = Y.T @ dL @ Y[:, :nev]           # P[j, k] = y_j^T dL y_k
+            tot = 0.0
+            for k in range(nev):
+                tot += g_lam[k] * P[k, k]
+                gk = g_V[:, k]
+                if gk.any():
+                    coef = Y.T @ gk               # g_k . y_j
+                    for j in range(n):
+                        if j != k:
+                            tot += coef[j] * P[j, k] / (lam[k] - lam[j])
+            cache[(a, b)] = tot
+        grad[q] = cache[(a, b)]
+    return grad, lam[:nev], Y[:, :nev]
 
 
 def _csr_matrix(rowptr, col, w, n):

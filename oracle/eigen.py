@@ -1,6 +1,7 @@
 """Eigenpairs of the graph Laplacian (oracle; test infrastructure only).
 
-Paper: Sec. 3.2 (problems L x = lambda x and L_C x = lambda D x), Sec. 3.3 and
+Paper: Sec. 3.2 (problems L_C x = lambda x, L_C x = lambda D x and
+L_N y = lambda y), Sec. 3.3 and
 Algorithm 1 (LOBPCG), Sec. 4 and Eq. 4 (number of eigenvectors).
 
 The plain definition of what the solver computes is "the d smallest eigenpairs
@@ -79,7 +80,8 @@ def rayleigh_ritz(S, LS, bd, nev, drop=1e-12):
 
 def lobpcg(rowptr, col, w, problem, X0, precond, tol, maxiter=10000,
            locking=True):
-    """Algorithm 1 (LOBPCG, Hetmaniuk-Lehoucq form) for L x = lambda B x.
+    """Algorithm 1 (LOBPCG, Hetmaniuk-Lehoucq form) for L x = lambda B x
+    (L = L_N and B = I for the normalized problem).
 
     precond: callable R -> H (the solve "M H = R"), or None for H = R.
     tol: bound on the relative residual rho_i of `laplacian.residual_norms`.
@@ -88,7 +90,7 @@ def lobpcg(rowptr, col, w, problem, X0, precond, tol, maxiter=10000,
     Returns (theta, X, iterations, rho).
     """
     bd = laplacian.bdiag(rowptr, col, w, problem)
-    L = lambda Z: laplacian.apply(rowptr, col, w, Z)
+    L = laplacian.operator(rowptr, col, w, problem)
     X = np.asarray(X0, dtype=np.float64)
     nev = X.shape[1]
     # initial Rayleigh-Ritz on the starting block

@@ -3,7 +3,9 @@
 Paper: Sec. 3.2 (Spectral Graph Partitioning).  The combinatorial Laplacian is
 L_C = D - A (Eq. 2); for weighted graphs the off-diagonal entries are the
 negated edge weights and the diagonal holds the sum of incident weights (the
-paragraph after Eq. 3).  The generalized problem is L_C x = lambda D x.
+paragraph after Eq. 3).  The generalized problem is L_C x = lambda D x.  The
+normalized Laplacian is L_N = I - D^-1/2 A D^-1/2 (the equation after Eq. 2),
+with the standard problem L_N y = lambda y.
 
 Reading taken (self-loops): the paper symmetrises inputs as A + A^T + I
 (Sec. 6.1) but Eq. 2 only uses off-diagonal adjacency, so self-loops carry no
@@ -17,6 +19,7 @@ import numpy as np
 
 COMBINATORIAL = 0
 GENERALIZED = 1
+NORMALIZED = 2
 
 
 def _weights(col, w):
@@ -85,6 +88,65 @@ def apply_sparse(rowptr, col, w, X):
     return (d[:, None] * X if X.ndim == 2 else d * X) - A @ X
 
 
+def apply_normalized(rowptr, col, w, X):
+    """Y = L_N X in FP64 from the definition L_N = I - D^-1/2 A D^-1/2:
+    y_i = x_i - sum_j w_ij x_j / sqrt(d_i d_j), d the weighted degrees."""
+    X = np.asarray(X, dtype=np.float64)
+    squeeze = X.ndim == 1
+    if squeeze:
+        X = X[:, None]
+    d = degrees(rowptr, col, w)
+    if (d <= 0).any():
+        raise ValueError("L_N needs every degree > 0")
+    ww = _weights(col, w)
+    r = row_index(rowptr)
+    c = np.asarray(col, dtype=np.int64)
+    contrib = (ww / np.sqrt(d[r] * d[c]))[:, None] * X[c]
+    AX = np.zeros_like(X)
+    np.add.at(AX, r, contrib)
+    Y = X - AX
+    return Y[:, 0] if squeeze else Y
+
+
+def apply_normalized_sparse(rowptr, col, w, X):
+    """Y = L_N X = X - D^-1/2 A D^-1/2 X with a library sparse product, for
+    graphs too large for `apply_normalized` (same operator, other rounding)."""
+    import scipy.sparse as sp
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    n = rowptr.size - 1
+    A = sp.csr_matrix((_weights(col, w), np.asarray(col, dtype=np.int64), rowptr), shape=(n, n))
+    d = np.asarray(A.sum(axis=1)).ravel()
+    if (d <= 0).any():
+        raise ValueError("L_N needs every degree > 0")
+    s = 1.0 / np.sqrt(d)
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        return X - s * (A @ (s * X))
+    return X - s[:, None] * (A @ (s[:, None] * X))
+
+
+def operator(rowptr, col, w, problem):
+    """The matrix of the eigenproblem as a callable: L_C for the
+    combinatorial and generalized problems, L_N for the normalized one."""
+    if problem == NORMALIZED:
+        return lambda Z: apply_normalized(rowptr, col, w, Z)
+    return lambda Z: apply(rowptr, col, w, Z)
+
+
+def dense_normalized(rowptr, col, w, n=None):
+    """Dense L_N entry by entry: 1 on the diagonal, -w_ij / sqrt(d_i d_j) off it."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    n = rowptr.size - 1 if n is None else n
+    ww = _weights(col, w)
+    d = degrees(rowptr, col, w)
+    L = np.eye(n)
+    for i in range(n):
+        for k in range(rowptr[i], rowptr[i + 1]):
+            j = int(col[k])
+            L[i, j] -= ww[k] / math.sqrt(d[i] * d[j])
+    return L
+
+
 def dense(rowptr, col, w, n=None):
     """Dense (L_C, d) built entry by entry from Eq. 2: L_ii = d_i, L_ij = -w_ij."""
     rowptr = np.asarray(rowptr, dtype=np.int64)
@@ -100,10 +162,11 @@ def dense(rowptr, col, w, n=None):
 
 
 def bdiag(rowptr, col, w, problem):
-    """Diagonal of B: ones (combinatorial, L x = lambda x) or the weighted degrees
-    (generalized, L x = lambda D x), Sec. 3.2."""
+    """Diagonal of B: ones (combinatorial L_C x = lambda x, normalized
+    L_N y = lambda y) or the weighted degrees (generalized, L_C x = lambda D x),
+    Sec. 3.2."""
     n = len(rowptr) - 1
-    if problem == COMBINATORIAL:
+    if problem in (COMBINATORIAL, NORMALIZED):
         return np.ones(n, dtype=np.float64)
     return degrees(rowptr, col, w)
 

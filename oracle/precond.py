@@ -7,7 +7,8 @@ Jacobi (Sec. 5.1).  Reading taken: the text writes M = diag(A)^-1 while
 Algorithm 1 solves M H = R; read together literally they would give
 H = diag(A) R, which is not a preconditioner.  The standard Jacobi step is
 taken instead: H = diag(L)^-1 R, i.e. h_ij = r_ij / d_i, for both the
-combinatorial and the generalized problem (diag L_C = D in both).
+combinatorial and the generalized problem (diag L_C = D in both).  For the
+normalized problem diag(L_N) = I, so Jacobi leaves R unchanged.
 
 Polynomial (Sec. 5.2).  The paper applies a degree-25 polynomial p(L) that
 needs only sparse matrix products and notes that Chebyshev polynomials need
@@ -18,7 +19,8 @@ interval [lo, hi], which yields h = p(L) r with deg p = k and
 hi is a guaranteed upper bound of the spectrum (Gershgorin: 2 max_i d_i for
 L_C, 2 for D^-1 L_C), so p > 0 on the whole spectrum and the preconditioner
 is symmetric positive definite.  For the generalized problem the iteration
-runs on D^-1 L_C with right-hand side D^-1 r.
+runs on D^-1 L_C with right-hand side D^-1 r; for the normalized problem on
+L_N, whose spectrum lies in [0, 2] (it is similar to D^-1 L_C).
 """
 from __future__ import annotations
 
@@ -32,11 +34,14 @@ def jacobi(R, d):
     return np.asarray(R, dtype=np.float64) / np.asarray(d, dtype=np.float64)[:, None]
 
 
-def chebyshev(rowptr, col, w, R, degree, lo, hi, dinv=None):
+def chebyshev(rowptr, col, w, R, degree, lo, hi, dinv=None,
+              problem=laplacian.COMBINATORIAL):
     """h = p(L) r column-wise by `degree` Chebyshev steps (degree SpMMs).
 
-    With dinv given, solves (D^-1 L) h = D^-1 r instead (generalized problem).
+    With dinv given, solves (D^-1 L) h = D^-1 r instead (generalized problem);
+    with problem NORMALIZED the matrix is L_N.
     """
+    L = laplacian.operator(rowptr, col, w, problem)
     R = np.asarray(R, dtype=np.float64)
     c = 0.5 * (hi + lo)
     e = 0.5 * (hi - lo)
@@ -47,7 +52,7 @@ def chebyshev(rowptr, col, w, R, degree, lo, hi, dinv=None):
     h_prev = np.zeros_like(R)
     h = rhs / c                     # first step from h = 0 needs no product
     for _ in range(degree):
-        res = rhs - scale(laplacian.apply(rowptr, col, w, h))
+        res = rhs - scale(L(h))
         rho = 1.0 / (2.0 * sigma - rho_prev)
         h_next = h + rho * rho_prev * (h - h_prev) + (2.0 * rho / e) * res
         h_prev, h = h, h_next
@@ -67,7 +72,7 @@ def chebyshev_scalar(x, degree, lo, hi):
 
 
 def gershgorin_bound(d, problem):
-    """Upper bound of the spectrum: 2 max d_i for L_C, 2 for D^-1 L_C."""
-    if problem == laplacian.GENERALIZED:
+    """Upper bound of the spectrum: 2 max d_i for L_C, 2 for D^-1 L_C and L_N."""
+    if problem in (laplacian.GENERALIZED, laplacian.NORMALIZED):
         return 2.0
     return 2.0 * float(np.max(d)) if len(d) else 0.0

@@ -14,7 +14,7 @@ from ._lib import (  # noqa: F401
     status_string, num_eigenvectors, options_default,
     laplacian_apply, precond_apply, eigensolve, split, quality, partition,
     eig_backward, workspace_size, set_workspace,
-    COMBINATORIAL, GENERALIZED, PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHEBYSHEV,
+    COMBINATORIAL, GENERALIZED, NORMALIZED, PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHEBYSHEV,
     FP64, MIXED, INIT_RANDOM, INIT_PIECEWISE, INIT_USER,
 )
 from .autograd import EigFn  # noqa: F401

@@ -11,7 +11,7 @@ library_path = os.path.join(PKG, "libsphynx.so")
 
 OK, NOT_CONVERGED = 0, 1
 UNIT, F32, F64 = 0, 1, 2
-COMBINATORIAL, GENERALIZED = 0, 1
+COMBINATORIAL, GENERALIZED, NORMALIZED = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHEBYSHEV = 0, 1, 2
 FP64, MIXED = 0, 1
 INIT_RANDOM, INIT_PIECEWISE, INIT_USER = 0, 1, 2
@@ -68,7 +68,7 @@ def _load():
         "sphx_workspace_size": (C.c_int, [vp, vp, C.c_int, C.POINTER(_Options),
                                           C.POINTER(C.c_size_t)]),
         "sphx_set_workspace": (C.c_int, [vp, vp, C.c_size_t]),
-        "sphx_laplacian_apply": (C.c_int, [vp, vp, C.c_int, C.c_int, vp, vp]),
+        "sphx_laplacian_apply": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int, vp, vp]),
         "sphx_precond_apply": (C.c_int, [vp, vp, C.POINTER(_Options), C.c_int, C.c_int, vp,
                                          vp]),
         "sphx_eigensolve": (C.c_int, [vp, vp, C.c_int, C.POINTER(_Options), vp, dp, vp,
@@ -120,7 +120,7 @@ class Options:
     problem: int = COMBINATORIAL
     precond: int = PRECOND_JACOBI
     cheb_degree: int = 25
-    cheb_ratio: float = 100.0
+    cheb_ratio: float = 1000.0
     precision: int = FP64
     tol: float = 1e-3
     max_iter: int = 10000
@@ -285,14 +285,15 @@ def set_workspace(h: Handle, buf) -> None:
                                     0 if buf is None else buf.numel() * buf.element_size()))
 
 
-def laplacian_apply(h: Handle, g: Graph, X, out=None):
-    """Y = L_C X for an n x m block (float32 or float64)."""
+def laplacian_apply(h: Handle, g: Graph, X, out=None, problem: int = COMBINATORIAL):
+    """Y = L X for an n x m block (float32 or float64): L_C, or L_N for the
+    normalized problem."""
     torch = _torch()
     X = X.contiguous()
     Y = torch.empty_like(X) if out is None else out
     m = 1 if X.dim() == 1 else X.shape[1]
-    h._check(lib.sphx_laplacian_apply(h.h, g.g, m, _dtype_code(X), C.c_void_p(_ptr(X)),
-                                      C.c_void_p(_ptr(Y))))
+    h._check(lib.sphx_laplacian_apply(h.h, g.g, problem, m, _dtype_code(X),
+                                      C.c_void_p(_ptr(X)), C.c_void_p(_ptr(Y))))
     return Y
 
 

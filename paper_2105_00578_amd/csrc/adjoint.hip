@@ -14,6 +14,12 @@
 // The first three groups are the bilinear forms (a-b)^T M1 (a-b) and
 // a^T M2 a + b^T M2 b with small nev x nev matrices built on the host.
 //
+// The normalized problem L_N y = lambda y has the eigenpairs (lambda, D^1/2 x)
+// of the generalized one.  With x = D^-1/2 y, the loss sees y through x and
+// through D^1/2, whose entries i and j move by 1/(2 sqrt(d)) when w_e does:
+//   dl/dw_e = [generalized gradient with dl/dx = D^1/2 dl/dy]
+//             + t_i + t_j,   t_i = sum_k (dl/dy_ik) y_ik / (2 d_i).
+//
 // mu_k comes from a projected preconditioned conjugate gradient run on all
 // columns at once (one Laplacian product per step): iterates stay in the
 // B-orthogonal complement of V through z = (I - V V^T B) J r, J the diagonal
@@ -206,6 +212,42 @@ __global__ __launch_bounds__(256) void k_edge_grad(int64_t n, const IdxT *rp,
   }
 }
 
+// normalized problem: X = D^-1/2 Y, GX = D^1/2 GY, t_i = sum_k GY_ik Y_ik / (2 d_i)
+__global__ void k_norm_prep(const double *Y, const double *GY, const double *d, int64_t n,
+                            int nev, double *X, double *GX, double *t) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double di = d[i];
+    const double r = sqrt(di);
+    double acc = 0.0;
+    for (int k = 0; k < nev; ++k) {
+      const double y = Y[i * nev + k];
+      X[i * nev + k] = y / r;
+      if (GY) {
+        const double gy = GY[i * nev + k];
+        GX[i * nev + k] = gy * r;
+        acc += gy * y;
+      }
+    }
+    t[i] = acc / (2.0 * di);
+  }
+}
+
+// grad[q] += t_i + t_j for every CSR entry q = (i, j); one wave per row
+template <typename IdxT>
+__global__ __launch_bounds__(256) void k_add_vertex_terms(int64_t n, const IdxT *rp,
+                                                          const int32_t *col, const double *t,
+                                                          double *grad) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x / 64;
+  for (int64_t i = (int64_t)blockIdx.x * wpb + threadIdx.x / 64; i < n;
+       i += (int64_t)gridDim.x * wpb) {
+    const double ti = t[i];
+    for (int64_t q = (int64_t)rp[i] + lane; q < (int64_t)rp[i + 1]; q += 64)
+      grad[q] += ti + t[col[q]];
+  }
+}
+
 constexpr int kSmallBlocks = 256;
 constexpr int kDotBlocks = 256;
 
@@ -213,7 +255,9 @@ constexpr int kDotBlocks = 256;
 
 size_t adjoint_scratch_bytes(int64_t n, int nev) {
   size_t blk = align_up(sizeof(double) * n * nev, 256);
-  return 7 * blk + align_up(sizeof(double) * kSmallBlocks * kMaxNev * kMaxNev, 256) +
+  // 7 blocks of the solve, 2 of the normalized transform, t
+  return 9 * blk + align_up(sizeof(double) * n, 256) +
+         align_up(sizeof(double) * kSmallBlocks * kMaxNev * kMaxNev, 256) +
          align_up(sizeof(double) * kMaxNev * kMaxNev, 256) * 2 + 4096;
 }
 
@@ -222,11 +266,34 @@ int eig_backward(sphx_graph *g, const SpmmPlan &plan, int problem, int nev,
                  double cg_tol, int cg_max_iter, const double *d64, double *grad,
                  void *scratch, void *pinned, hipStream_t s, std::string *err) {
   const int64_t n = g->n;
-  const bool gen = problem == SPHX_GENERALIZED;
-  const double *bd = gen ? d64 : nullptr;
   Arena a;
   a.base = static_cast<char *>(scratch);
   size_t blk = (size_t)n * nev;
+  if (problem == SPHX_NORMALIZED) {
+    double *Xn = a.take<double>(blk);
+    double *GXn = a.take<double>(blk);
+    double *t = a.take<double>(n);
+    hipLaunchKernelGGL(k_norm_prep, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, V, gV, d64,
+                       n, nev, Xn, GXn, t);
+    int r = eig_backward(g, plan, SPHX_GENERALIZED, nev, lam, Xn, g_vals, gV ? GXn : nullptr,
+                         cg_tol, cg_max_iter, d64, grad, a.base + align_up(a.off, 256), pinned, s,
+                         err);
+    if (r < 0 || !gV) return r;
+    unsigned gb = grid_for(n, 4, 1 << 16);
+    if (g->rp64)
+      hipLaunchKernelGGL((k_add_vertex_terms<int64_t>), dim3(gb), dim3(256), 0, s, n,
+                         (const int64_t *)g->rowptr, g->col, (const double *)t, grad);
+    else
+      hipLaunchKernelGGL((k_add_vertex_terms<int32_t>), dim3(gb), dim3(256), 0, s, n,
+                         (const int32_t *)g->rowptr, g->col, (const double *)t, grad);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+      *err = "adjoint kernel failed";
+      return SPHX_E_HIP;
+    }
+    return r;
+  }
+  const bool gen = problem == SPHX_GENERALIZED;
+  const double *bd = gen ? d64 : nullptr;
   double *MU = a.take<double>(blk);
   double *Rr = a.take<double>(blk);
   double *Z = a.take<double>(blk);

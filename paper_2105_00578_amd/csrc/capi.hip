@@ -43,7 +43,7 @@ constexpr int kRqBlocks = 256;
 // Workspace layout of a solve (also used for sizing with count_only).
 template <typename T>
 struct SolveWs {
-  double *d64, *dinv;
+  double *d64, *dinv, *sq, *rsq;
   T *X, *LX, *R, *B1, *B2, *LH, *P, *LP;
   double *X64, *LX64;
   double *norm_partials, *gram_partials, *gram_out, *Y, *theta;
@@ -64,6 +64,8 @@ void layout(Arena &a, SolveWs<T> &w, int64_t n, int m, int K, size_t plan_b,
             bool want_split) {
   w.d64 = a.take<double>(n);
   w.dinv = a.take<double>(n);
+  w.sq = a.take<double>(n);
+  w.rsq = a.take<double>(n);
   const size_t blk = (size_t)n * padded_ld(m, sizeof(T));
   w.X = a.take<T>(blk);
   w.LX = a.take<T>(blk);
@@ -107,7 +109,9 @@ void layout(Arena &a, SolveWs<T> &w, int64_t n, int m, int K, size_t plan_b,
 
 bool valid_options(const sphx_options *o) {
   if (!o) return false;
-  if (o->problem != SPHX_COMBINATORIAL && o->problem != SPHX_GENERALIZED) return false;
+  if (o->problem != SPHX_COMBINATORIAL && o->problem != SPHX_GENERALIZED &&
+      o->problem != SPHX_NORMALIZED)
+    return false;
   if (o->precond < SPHX_PRECOND_NONE || o->precond > SPHX_PRECOND_CHEBYSHEV) return false;
   if (o->precond == SPHX_PRECOND_CHEBYSHEV && (o->cheb_degree < 1 || !(o->cheb_ratio > 1.0)))
     return false;
@@ -123,6 +127,16 @@ ColMap identity_map(int m) {
   c.count = m;
   for (int i = 0; i < kMaxNev; ++i) c.col[i] = i < m ? i : 0;
   return c;
+}
+
+// sq = sqrt(d), rsq = 1 / sqrt(d): the congruence between L_N and (L_C, D)
+__global__ void k_sqrt_pair(const double *d, double *sq, double *rsq, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double r = sqrt(d[i]);
+    sq[i] = r;
+    rsq[i] = 1.0 / r;
+  }
 }
 
 __global__ void k_inverse(const double *d, double *dinv, int64_t n) {
@@ -281,10 +295,16 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   int tid = pl.begin(PH_SETUP, 0.0, s);
   DegreeStats ds;
   SPHX_TRY(compute_degrees(g, w.d64, nullptr, w.deg_scratch, &ds, h->pinned_small, s));
-  const bool gen = o.problem == SPHX_GENERALIZED;
+  // the normalized problem runs as the generalized pencil in x = D^-1/2 y
+  const bool norm = o.problem == SPHX_NORMALIZED;
+  const bool gen = o.problem != SPHX_COMBINATORIAL;
   if ((gen || o.precond == SPHX_PRECOND_JACOBI) && !(ds.min_wdeg > 0.0))
     return set_err(h, SPHX_E_INVALID_ARG,
-                   "isolated vertex: the generalized problem and Jacobi need all degrees > 0");
+                   "isolated vertex: the generalized and normalized problems and Jacobi "
+                   "need all degrees > 0");
+  if (norm)
+    hipLaunchKernelGGL(k_sqrt_pair, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, w.d64, w.sq,
+                       w.rsq, n);
   Arena pa;
   pa.base = wsbase + w.plan_off;
   pa.cap = plan_bytes(g);
@@ -321,6 +341,9 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     launch_init_piecewise<T>(w.X, n, m, ld, s);
   else
     launch_init_random<T>(w.X, n, m, ld, o.seed, s);
+  if (norm)   // the initial block is given in y; x = D^-1/2 y
+    hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for((int64_t)n * ld, 256, 4096)), dim3(256),
+                       0, s, (const T *)w.X, (const double *)w.rsq, 1.0, w.X, n, ld);
   tid = pl.begin(PH_SPMM, spmm_bytes(g, w.plan, m, vs, 2, 0), s);
   SPHX_TRY(vspmm_store<T>(g, w.plan, w.X, ld, m, EpiStoreP<T>{w.LX, ld}, s));
   pl.end(tid, s);
@@ -445,6 +468,9 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   }
   for (int q = 0; q < m; ++q)
     launch_copy_cols<T>(w.X + perm[q], ld, vecs_out + q, m, n, 1, s);
+  if (norm)   // y = D^1/2 x; ||y||_2 = ||x||_D, so the same scale normalises y
+    hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for((int64_t)n * m, 256, 4096)), dim3(256),
+                       0, s, (const T *)vecs_out, (const double *)w.sq, 1.0, vecs_out, n, m);
   SPHX_TRY(normalize_columns<T>(vecs_out, n, m, scale, w.norm_scratch, s));
   if (stats) {
     stats->iterations = it;
@@ -526,11 +552,12 @@ void sphx_options_default(sphx_options *o, int regular, int precond) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
   o->precond = precond;
-  o->problem = regular ? SPHX_COMBINATORIAL : SPHX_GENERALIZED;
+  o->problem = regular ? SPHX_COMBINATORIAL
+                       : (precond == SPHX_PRECOND_CHEBYSHEV ? SPHX_NORMALIZED : SPHX_GENERALIZED);
   o->tol = regular ? 1e-3 : 1e-2;
   o->init = regular ? SPHX_INIT_RANDOM : SPHX_INIT_PIECEWISE;
   o->cheb_degree = 25;
-  o->cheb_ratio = 100.0;
+  o->cheb_ratio = 1000.0;
   o->precision = SPHX_FP64;
   o->max_iter = 10000;
   o->seed = 0x5eed;
@@ -634,37 +661,72 @@ int sphx_set_workspace(sphx_handle *h, void *ptr, size_t bytes) {
   return SPHX_OK;
 }
 
-int sphx_laplacian_apply(sphx_handle *h, sphx_graph *g, int m, int dtype, const void *X,
-                         void *Y) {
+int sphx_laplacian_apply(sphx_handle *h, sphx_graph *g, int problem, int m, int dtype,
+                         const void *X, void *Y) {
   if (!h || !g || !X || !Y || m < 1 || m > kMaxNev ||
-      (dtype != SPHX_F32 && dtype != SPHX_F64))
+      (dtype != SPHX_F32 && dtype != SPHX_F64) ||
+      (problem != SPHX_COMBINATORIAL && problem != SPHX_GENERALIZED &&
+       problem != SPHX_NORMALIZED))
     return SPHX_E_INVALID_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  hipStream_t s = h->stream;
+  const bool norm = problem == SPHX_NORMALIZED;
+  const size_t blk = (size_t)g->n * m * bytes_of(dtype);
   char *ws = nullptr;
-  size_t need = plan_bytes(g) + align_up(sizeof(double) * g->n, 256) +
-                4 * kDegBlocksMax * sizeof(double) + 1024;
+  size_t need = plan_bytes(g) + 3 * align_up(sizeof(double) * g->n, 256) +
+                align_up(4 * kDegBlocksMax * sizeof(double), 256) +
+                (norm ? align_up(blk, 256) : 0) + 1024;
   SPHX_TRY(get_workspace(h, need, &ws));
+  Arena a;
+  a.base = ws;
+  double *d64 = a.take<double>(g->n);
+  double *sq = a.take<double>(g->n);
+  double *rsq = a.take<double>(g->n);
+  double *degs = a.take<double>(4 * kDegBlocksMax);
+  char *tmp = norm ? a.take<char>(blk) : nullptr;
   DegreeStats ds;
-  double *d64 = reinterpret_cast<double *>(ws);
-  char *rest = ws + align_up(sizeof(double) * g->n, 256);
-  SPHX_TRY(compute_degrees(g, d64, nullptr, rest, &ds, h->pinned_small, h->stream));
-  Arena pa;
-  pa.base = rest + align_up(4 * kDegBlocksMax * sizeof(double), 256);
+  SPHX_TRY(compute_degrees(g, d64, nullptr, degs, &ds, h->pinned_small, s));
   SpmmPlan plan;
-  SPHX_TRY(build_plan(g, pa, &plan, ds, h->pinned_small, h->stream));
+  SPHX_TRY(build_plan(g, a, &plan, ds, h->pinned_small, s));
+  const int64_t n = g->n;
+  const void *src = X;
+  if (norm) {
+    // L_N X = D^-1/2 (L_C (D^-1/2 X))
+    if (!(ds.min_wdeg > 0)) return set_err(h, SPHX_E_INVALID_ARG, "isolated vertex");
+    hipLaunchKernelGGL(k_sqrt_pair, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, d64, sq, rsq,
+                       n);
+    if (dtype == SPHX_F32)
+      hipLaunchKernelGGL(k_scale_rows<float>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s,
+                         (const float *)X, (const double *)rsq, 1.0, (float *)tmp, n, m);
+    else
+      hipLaunchKernelGGL(k_scale_rows<double>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0,
+                         s, (const double *)X, (const double *)rsq, 1.0, (double *)tmp, n, m);
+    src = tmp;
+  }
   ColMap cm = identity_map(m);
   // rows that are whole 16-byte vectors take the vector-row kernels
-  const bool vec = (m * bytes_of(dtype)) % 16 == 0 && ((uintptr_t)X % 16) == 0 &&
+  const bool vec = (m * bytes_of(dtype)) % 16 == 0 && ((uintptr_t)src % 16) == 0 &&
                    ((uintptr_t)Y % 16) == 0;
+  int r;
   if (dtype == SPHX_F32)
-    return vec ? vspmm_store<float>(g, plan, (const float *)X, m, m,
-                                    EpiStoreP<float>{(float *)Y, m}, h->stream)
-               : spmm_store<float>(g, plan, (const float *)X, m, cm,
-                                   EpiStoreP<float>{(float *)Y, m}, h->stream);
-  return vec ? vspmm_store<double>(g, plan, (const double *)X, m, m,
-                                   EpiStoreP<double>{(double *)Y, m}, h->stream)
-             : spmm_store<double>(g, plan, (const double *)X, m, cm,
-                                  EpiStoreP<double>{(double *)Y, m}, h->stream);
+    r = vec ? vspmm_store<float>(g, plan, (const float *)src, m, m,
+                                 EpiStoreP<float>{(float *)Y, m}, s)
+            : spmm_store<float>(g, plan, (const float *)src, m, cm,
+                                EpiStoreP<float>{(float *)Y, m}, s);
+  else
+    r = vec ? vspmm_store<double>(g, plan, (const double *)src, m, m,
+                                  EpiStoreP<double>{(double *)Y, m}, s)
+            : spmm_store<double>(g, plan, (const double *)src, m, cm,
+                                 EpiStoreP<double>{(double *)Y, m}, s);
+  if (r != SPHX_OK || !norm) return r;
+  if (dtype == SPHX_F32)
+    hipLaunchKernelGGL(k_scale_rows<float>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s,
+                       (const float *)Y, (const double *)rsq, 1.0, (float *)Y, n, m);
+  else
+    hipLaunchKernelGGL(k_scale_rows<double>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s,
+                       (const double *)Y, (const double *)rsq, 1.0, (double *)Y, n, m);
+  SPHX_HIP(h, hipGetLastError());
+  return SPHX_OK;
 }
 
 int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int m,
@@ -675,14 +737,17 @@ int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int
   if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
   hipStream_t s = h->stream;
   size_t blk = (size_t)g->n * m * bytes_of(dtype);
-  size_t need = plan_bytes(g) + 2 * align_up(sizeof(double) * g->n, 256) +
-                2 * align_up(blk, 256) + 4 * kDegBlocksMax * sizeof(double) + 4096;
+  size_t need = plan_bytes(g) + 4 * align_up(sizeof(double) * g->n, 256) +
+                3 * align_up(blk, 256) + 4 * kDegBlocksMax * sizeof(double) + 4096;
   char *ws = nullptr;
   SPHX_TRY(get_workspace(h, need, &ws));
   Arena a;
   a.base = ws;
   double *d64 = a.take<double>(g->n);
   double *dinv = a.take<double>(g->n);
+  double *sq = a.take<double>(g->n);
+  double *rsq = a.take<double>(g->n);
+  char *b0 = a.take<char>(blk);
   double *degs = a.take<double>(4 * kDegBlocksMax);
   char *b1 = a.take<char>(blk);
   char *b2 = a.take<char>(blk);
@@ -691,7 +756,9 @@ int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int
   SpmmPlan plan;
   SPHX_TRY(build_plan(g, a, &plan, ds, h->pinned_small, s));
   const int64_t n = g->n;
-  if (o->precond == SPHX_PRECOND_NONE) {
+  const bool norm = o->problem == SPHX_NORMALIZED;
+  if (o->precond == SPHX_PRECOND_NONE || (norm && o->precond == SPHX_PRECOND_JACOBI)) {
+    // diag(L_N) = I: Jacobi is the identity for the normalized problem
     SPHX_HIP(h, hipMemcpyAsync(H, R, blk, hipMemcpyDeviceToDevice, s));
   } else if (o->precond == SPHX_PRECOND_JACOBI) {
     if (!(ds.min_wdeg > 0)) return set_err(h, SPHX_E_INVALID_ARG, "isolated vertex");
@@ -702,8 +769,21 @@ int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int
       hipLaunchKernelGGL(k_jacobi<double>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s,
                          (const double *)R, d64, (double *)H, n, m);
   } else {
-    const bool gen = o->problem == SPHX_GENERALIZED;
+    const bool gen = o->problem != SPHX_COMBINATORIAL;
     if (gen && !(ds.min_wdeg > 0)) return set_err(h, SPHX_E_INVALID_ARG, "isolated vertex");
+    if (norm) {
+      // p(L_N) r = D^1/2 [p(D^-1 L_C) D^-1] (D^1/2 r): the generalized iteration
+      // on D^1/2 r, scaled by D^1/2 at the end
+      hipLaunchKernelGGL(k_sqrt_pair, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, d64, sq,
+                         rsq, n);
+      if (dtype == SPHX_F32)
+        hipLaunchKernelGGL(k_scale_rows<float>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0,
+                           s, (const float *)R, (const double *)sq, 1.0, (float *)b0, n, m);
+      else
+        hipLaunchKernelGGL(k_scale_rows<double>, dim3(grid_for(n * m, 256, 4096)), dim3(256),
+                           0, s, (const double *)R, (const double *)sq, 1.0, (double *)b0, n, m);
+      R = b0;
+    }
     double hi = gen ? 2.0 : 2.0 * ds.max_wdeg;
     ChebCoef ck = cheb_coef(o->cheb_degree, hi / o->cheb_ratio, hi);
     const double *dv = nullptr;
@@ -715,16 +795,25 @@ int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int
     int64_t calls = 0, pcalls = 0;
     h->plog.reset();
     h->plog.on = false;
+    const double *post = norm ? sq : nullptr;
     if (dtype == SPHX_F32) {
       float *res = nullptr;
       SPHX_TRY(cheb_apply<float>(h, g, plan, m, m, cm, (const float *)R, (float *)b1,
                                  (float *)b2, ck, dv, s, &res, &calls, &pcalls));
-      SPHX_HIP(h, hipMemcpyAsync(H, res, blk, hipMemcpyDeviceToDevice, s));
+      if (post)
+        hipLaunchKernelGGL(k_scale_rows<float>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0,
+                           s, (const float *)res, post, 1.0, (float *)H, n, m);
+      else
+        SPHX_HIP(h, hipMemcpyAsync(H, res, blk, hipMemcpyDeviceToDevice, s));
     } else {
       double *res = nullptr;
       SPHX_TRY(cheb_apply<double>(h, g, plan, m, m, cm, (const double *)R, (double *)b1,
                                   (double *)b2, ck, dv, s, &res, &calls, &pcalls));
-      SPHX_HIP(h, hipMemcpyAsync(H, res, blk, hipMemcpyDeviceToDevice, s));
+      if (post)
+        hipLaunchKernelGGL(k_scale_rows<double>, dim3(grid_for(n * m, 256, 4096)), dim3(256),
+                           0, s, (const double *)res, post, 1.0, (double *)H, n, m);
+      else
+        SPHX_HIP(h, hipMemcpyAsync(H, res, blk, hipMemcpyDeviceToDevice, s));
     }
   }
   SPHX_HIP(h, hipGetLastError());
@@ -797,7 +886,10 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
     stats->gb_spmm = gb[PH_SPMM];
     stats->gb_precond = gb[PH_PRECOND];
   }
-  return hit_max ? SPHX_NOT_CONVERGED : SPHX_OK;
+  if (hit_max)
+    return set_err(h, SPHX_NOT_CONVERGED,
+                   "max_iter reached before every relative residual met tol");
+  return SPHX_OK;
 }
 
 int sphx_eigensolve(sphx_handle *h, sphx_graph *g, int nev, const sphx_options *o,
@@ -950,7 +1042,8 @@ int sphx_eig_backward(sphx_handle *h, sphx_graph *g, int problem, int nev,
                       const void *g_vecs, double cg_tol, int cg_max_iter, void *grad_w) {
   if (!h || !g || !eigvals || !eigvecs || !grad_w || nev < 1 || nev > kMaxNev ||
       nev >= g->n || !(cg_tol > 0) || cg_max_iter < 1 ||
-      (problem != SPHX_COMBINATORIAL && problem != SPHX_GENERALIZED))
+      (problem != SPHX_COMBINATORIAL && problem != SPHX_GENERALIZED &&
+       problem != SPHX_NORMALIZED))
     return SPHX_E_INVALID_ARG;
   if (g->wdt == SPHX_F32)
     return set_err(h, SPHX_E_INVALID_ARG, "the adjoint needs F64 (or unit) edge weights");
@@ -968,7 +1061,7 @@ int sphx_eig_backward(sphx_handle *h, sphx_graph *g, int problem, int nev,
   SPHX_TRY(compute_degrees(g, d64, nullptr, degs, &ds, h->pinned_small, h->stream));
   SpmmPlan plan;
   SPHX_TRY(build_plan(g, a, &plan, ds, h->pinned_small, h->stream));
-  if (problem == SPHX_GENERALIZED && !(ds.min_wdeg > 0))
+  if (problem != SPHX_COMBINATORIAL && !(ds.min_wdeg > 0))
     return set_err(h, SPHX_E_INVALID_ARG, "isolated vertex");
   char *scratch = a.take<char>(adjoint_scratch_bytes(g->n, nev));
   std::string err;

@@ -89,3 +89,44 @@ def test_homogeneity_identities(problem):
     gr = adjoint.grad_projected(g.rowptr, g.col, g.w, problem, lam, V, None, C)
     expect = 0.0 if problem == lap.COMBINATORIAL else -0.5 * np.sum(C * V)
     assert g.w[und] @ gr[und] == pytest.approx(expect, rel=1e-8, abs=1e-9)
+
+
+def _loss_normalized(g, w, nev, a, C):
+    LN = lap.dense_normalized(g.rowptr, g.col, w)
+    lam, Y = eigen.smallest_dense(LN, np.ones(g.n), nev)
+    return a @ lam + np.sum(C * Y)
+
+
+def test_normalized_dense_gradient_matches_central_differences():
+    g = _graph(12, 0.3, 21)
+    nev = 4
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal(nev)
+    C = rng.standard_normal((g.n, nev))
+    grad, lam, Y = adjoint.grad_dense_normalized(g.rowptr, g.col, g.w, nev, a, C)
+    mate = _mate(g)
+    assert np.allclose(grad, grad[mate])
+    h = 1e-6
+    for e in _undirected(g):
+        wp = g.w.copy(); wp[e] += h; wp[mate[e]] += h
+        wm = g.w.copy(); wm[e] -= h; wm[mate[e]] -= h
+        fd = (_loss_normalized(g, wp, nev, a, C) - _loss_normalized(g, wm, nev, a, C)) / (2 * h)
+        assert fd == pytest.approx(grad[e], rel=1e-6, abs=1e-8)
+
+
+def test_normalized_homogeneity_and_generalized_eigenvalue_gradient():
+    # L_N(c w) = L_N(w): eigenvalues and unit eigenvectors are degree-0
+    # homogeneous, so w . grad = 0 for any loss; the eigenvalues equal the
+    # generalized ones, so their gradients agree with the generalized formula
+    g = _graph(30, 0.15, 9)
+    nev = 4
+    und = _undirected(g)
+    rng = np.random.default_rng(6)
+    a = rng.standard_normal(nev)
+    C = rng.standard_normal((g.n, nev))
+    grad, lam, Y = adjoint.grad_dense_normalized(g.rowptr, g.col, g.w, nev, a, C)
+    assert abs(g.w[und] @ grad[und]) < 1e-9
+    gn, _, _ = adjoint.grad_dense_normalized(g.rowptr, g.col, g.w, nev, a, None)
+    gg, lam_g, _ = adjoint.grad_dense(g.rowptr, g.col, g.w, lap.GENERALIZED, nev, a, None)
+    assert np.allclose(lam, lam_g, atol=1e-12)
+    assert np.allclose(gn, gg, rtol=1e-8, atol=1e-11)

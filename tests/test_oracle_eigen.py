@@ -62,19 +62,25 @@ def _random_weighted(n, p, seed):
     return graphgen.csr_from_edges(n, u, v, w)
 
 
-@pytest.mark.parametrize("problem", [lap.COMBINATORIAL, lap.GENERALIZED])
+@pytest.mark.parametrize("problem", [lap.COMBINATORIAL, lap.GENERALIZED, lap.NORMALIZED])
 @pytest.mark.parametrize("pc", ["none", "jacobi", "cheb"])
 def test_lobpcg_matches_dense_definition(problem, pc):
     g = _random_weighted(120, 0.04, 11)
     L, d = lap.dense(g.rowptr, g.col, g.w)
     bd = lap.bdiag(g.rowptr, g.col, g.w, problem)
     nev = 4
+    if problem == lap.NORMALIZED:
+        L = lap.dense_normalized(g.rowptr, g.col, g.w)
+        diag = np.ones(g.n)
+    else:
+        diag = d
     lam, V = eigen.smallest_dense(L, bd, nev)
     hi = precond.gershgorin_bound(d, problem)
     dinv = 1.0 / d if problem == lap.GENERALIZED else None
     pcs = {"none": None,
-           "jacobi": lambda R: precond.jacobi(R, d),
-           "cheb": lambda R: precond.chebyshev(g.rowptr, g.col, g.w, R, 8, hi / 30, hi, dinv)}
+           "jacobi": lambda R: precond.jacobi(R, diag),
+           "cheb": lambda R: precond.chebyshev(g.rowptr, g.col, g.w, R, 8, hi / 30, hi, dinv,
+                                               problem=problem)}
     X0 = graphgen.normal_block(g.n, nev, 2)
     theta, X, it, rho = eigen.lobpcg(g.rowptr, g.col, g.w, problem, X0, pcs[pc], 1e-9)
     assert rho.max() <= 1e-8

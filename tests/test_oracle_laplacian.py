@@ -113,3 +113,61 @@ def test_residual_norm_hand_example():
     # ||x||_D = sqrt(2); scale = max(2, 2) * sqrt(2)
     rho = lap.residual_norms(LX, X, theta, np.array([2.0, 2.0]))
     assert rho[1] == pytest.approx(2.0 / (2.0 * np.sqrt(2.0)))
+
+
+# ---- normalized Laplacian L_N = I - D^-1/2 A D^-1/2 (the equation after Eq. 2)
+
+def test_normalized_entrywise_dense_matches_apply():
+    g, _ = _random_weighted()
+    LN = lap.dense_normalized(g.rowptr, g.col, g.w)
+    X = np.random.default_rng(4).standard_normal((g.n, 3))
+    assert np.allclose(lap.apply_normalized(g.rowptr, g.col, g.w, X), LN @ X, rtol=0, atol=1e-13)
+    assert np.allclose(LN, LN.T, rtol=0, atol=1e-15)
+    assert np.allclose(np.diag(LN), 1.0)
+
+
+def test_normalized_eigenpairs_are_scaled_generalized_ones():
+    # L_C x = lambda D x  <=>  L_N (D^1/2 x) = lambda (D^1/2 x): a library
+    # generalized eigensolver on the (pinned) dense L_C and D fixes L_N's pairs
+    import scipy.linalg
+    g, _ = _random_weighted()
+    L, d = lap.dense(g.rowptr, g.col, g.w)
+    lam, X = scipy.linalg.eigh(L, np.diag(d))
+    Y = np.sqrt(d)[:, None] * X
+    LY = lap.apply_normalized(g.rowptr, g.col, g.w, Y)
+    assert np.abs(LY - Y * lam[None, :]).max() < 1e-11
+    assert lam.min() > -1e-12 and lam.max() <= 2.0 + 1e-12
+
+
+def test_normalized_trivial_vector_and_regular_cycle_closed_form():
+    n = 12
+    u = np.arange(n)
+    v = (u + 1) % n
+    g = graphgen.csr_from_edges(n, u, v)
+    # 2-regular: L_N = L_C / 2, eigenpairs (1 - cos(2 pi k / n), cos(2 pi k i / n))
+    i = np.arange(n)
+    for k in range(n // 2 + 1):
+        x = np.cos(2 * np.pi * k * i / n)
+        y = lap.apply_normalized(g.rowptr, g.col, None, x)
+        assert np.abs(y - (1 - np.cos(2 * np.pi * k / n)) * x).max() < 1e-13
+    # even cycle is bipartite: eigenvalue 2 on the alternating vector
+    alt = (-1.0) ** i
+    assert np.abs(lap.apply_normalized(g.rowptr, g.col, None, alt) - 2 * alt).max() < 1e-14
+    # D^1/2 1 is in the kernel on an irregular weighted graph
+    gw, _ = _random_weighted()
+    s = np.sqrt(lap.degrees(gw.rowptr, gw.col, gw.w))
+    assert np.abs(lap.apply_normalized(gw.rowptr, gw.col, gw.w, s)).max() < 1e-13 * s.max()
+
+
+def test_normalized_rejects_isolated_vertex():
+    g = graphgen.csr_from_edges(3, np.array([0]), np.array([1]))
+    with pytest.raises(ValueError):
+        lap.apply_normalized(g.rowptr, g.col, None, np.ones(3))
+
+
+def test_normalized_sparse_form_matches_definition():
+    g, _ = _random_weighted()
+    X = np.random.default_rng(5).standard_normal((g.n, 3))
+    a = lap.apply_normalized(g.rowptr, g.col, g.w, X)
+    b = lap.apply_normalized_sparse(g.rowptr, g.col, g.w, X)
+    assert np.allclose(a, b, rtol=0, atol=1e-13 * np.abs(X).max() * 10)

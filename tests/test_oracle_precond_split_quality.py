@@ -49,6 +49,19 @@ def test_chebyshev_generalized_on_torus():
     assert np.allclose(H[:, 0], p * x / 4, atol=1e-12)
 
 
+def test_chebyshev_normalized_on_torus():
+    n, u, v = cf.torus_edges(5, 4)
+    g = graphgen.csr_from_edges(n, u, v)
+    # 4-regular: L_N = L_C / 4, so the torus eigenvector has eigenvalue lam/4
+    x = np.cos(2 * np.pi * 2 * (np.arange(n) % 5) / 5)
+    lam = 2 - 2 * np.cos(2 * np.pi * 2 / 5)
+    H = precond.chebyshev(g.rowptr, g.col, None, x[:, None], 6, 0.1, 2.0,
+                          problem=lap.NORMALIZED)
+    p = precond.chebyshev_scalar(lam / 4, 6, 0.1, 2.0)
+    assert np.allclose(H[:, 0], p * x, atol=1e-12)
+    assert precond.gershgorin_bound(np.array([3.0, 9.0]), lap.NORMALIZED) == 2.0
+
+
 def test_chebyshev_polynomial_positive_on_spectrum():
     xs = np.linspace(1e-6, 12.0, 2001)
     assert np.all(precond.chebyshev_scalar(xs, 25, 12.0 / 30, 12.0) > 0)

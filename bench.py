@@ -125,6 +125,7 @@ def run(args):
             cheb_gbs=gbp / (msp * 1e-3) if msp > 0 else 0.0,
             cheb_avg_us=msp / max(1, sum(s.precond_calls for s in sts)) * 1e3,
             cheb_calls=sum(s.precond_calls for s in sts),
+            avg_active_cols=sum(s.precond_cols for s in sts) / max(1, sum(s.iterations for s in sts)),
             spmm_other_gbs=gbs / (mss * 1e-3) if mss > 0 else 0.0,
             eig_relerr_max=relerr, trivial_rel=trivial, subspace_sin=sin,
             phases_ms={k: round(v / 1.0, 3) for k, v in st.phases_ms.items()},
@@ -161,6 +162,7 @@ def run(args):
             "kernel": "Chebyshev-step Laplacian product (FP32, 7-point rows)",
             "avg_launch_us": round(mx["cheb_avg_us"], 3),
             "launches": mx["cheb_calls"],
+            "avg_active_cols": round(mx["avg_active_cols"], 3),
         },
         "time_to_eigvecs_ms": {"mixed": round(mx["time_to_eigvecs_ms"], 3),
                                "fp64": round(f64["time_to_eigvecs_ms"], 3)},

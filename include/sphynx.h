@@ -126,6 +126,8 @@ typedef struct sphx_stats {
                                     in ms_spmm / ms_precond: index arrays
                                     once, each block entry read or written
                                     once (gathered rows counted once)         */
+    int64_t precond_cols; /* sum over preconditioner applies of the number of
+                             active (unconverged) columns they served         */
 } sphx_stats;
 
 /* ---------------------------------------------------------------- basics */

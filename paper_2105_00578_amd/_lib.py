@@ -40,7 +40,7 @@ class _Stats(C.Structure):
                 ("ms_update", C.c_double), ("ms_split", C.c_double),
                 ("ms_quality", C.c_double), ("spmm_calls", C.c_int64),
                 ("precond_calls", C.c_int64), ("gb_spmm", C.c_double),
-                ("gb_precond", C.c_double)]
+                ("gb_precond", C.c_double), ("precond_cols", C.c_int64)]
 
 
 def _load():
@@ -160,6 +160,7 @@ class Stats:
     precond_calls: int
     gb_spmm: float
     gb_precond: float
+    precond_cols: int
 
 
 def _stats(s: _Stats, nev: int) -> Stats:
@@ -167,7 +168,7 @@ def _stats(s: _Stats, nev: int) -> Stats:
               ("setup", "spmm", "precond", "gram", "rr", "update", "split", "quality")}
     return Stats(s.iterations, s.converged, s.restarts, s.graph_regular, s.max_degree,
                  s.avg_degree, list(s.rho[: min(nev, 32)]), s.ms_total, phases,
-                 s.spmm_calls, s.precond_calls, s.gb_spmm, s.gb_precond)
+                 s.spmm_calls, s.precond_calls, s.gb_spmm, s.gb_precond, s.precond_cols)
 
 
 def _torch():

@@ -287,7 +287,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
           bool *hit_max) {
   hipStream_t s = h->stream;
   const int64_t n = g->n;
-  int64_t calls = 0, pcalls = 0;
+  int64_t calls = 0, pcalls = 0, pcols = 0;
   Timer tall;
   tall.start(s);
   PhaseLog &pl = h->plog;
@@ -388,6 +388,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     act.count = hs->nact;
     for (int q = 0; q < kMaxNev; ++q) act.col[q] = q < hs->nact ? hs->act[q] : 0;
     T *H = w.B1;
+    pcols += act.count;
     if (o.precond == SPHX_PRECOND_CHEBYSHEV) {
       SPHX_TRY(cheb_apply<T>(h, g, w.plan, m, ld, act, w.R, w.B1, w.B2, ck, dinv, s, &H, &calls,
                              &pcalls));
@@ -478,6 +479,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     stats->restarts = restarts;
     stats->spmm_calls = calls;
     stats->precond_calls = pcalls;
+    stats->precond_cols = pcols;
     stats->ms_total = tall.stop(s);
   } else {
     SPHX_HIP(h, hipStreamSynchronize(s));

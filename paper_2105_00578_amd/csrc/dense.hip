@@ -520,33 +520,41 @@ __global__ __launch_bounds__(256) void k_update(T *X, const T *__restrict__ H, T
 
 // ------------------------------------------------------------- finalize
 // Sum the sum-major partials (sum q of block b at partials[q * stride + b])
-// over b in a fixed order -> out[q], q < 2 * kMaxNev.  Each wavefront takes
-// every fourth sum: lanes stride over the blocks, then a butterfly.
-__device__ void sum_partials_block(const double *partials, int nblocks, int stride,
+// over b in a fixed order -> out[q] for the 2m sums q < m and
+// kMaxNev <= q < kMaxNev + m.  One wavefront per sum: lanes stride over the
+// blocks into eight accumulators (independent loads in flight), which are
+// combined in a fixed tree, then a butterfly across lanes.
+constexpr int kSumThreads = 1024;
+__device__ void sum_partials_block(const double *partials, int nblocks, int stride, int m,
                                    double *out) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  for (int q = wave; q < 2 * kMaxNev; q += 4) {
+  const int nw = blockDim.x >> 6;
+  for (int j = wave; j < 2 * m; j += nw) {
+    const int q = j < m ? j : kMaxNev + (j - m);
     const double *p = partials + (int64_t)q * stride;
-    double v0 = 0.0, v1 = 0.0;
+    double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int b = lane;
-    for (; b + 64 < nblocks; b += 128) {
-      v0 += p[b];
-      v1 += p[b + 64];
+    for (; b + 7 * 64 < nblocks; b += 8 * 64) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] += p[b + u * 64];
     }
-    if (b < nblocks) v0 += p[b];
-    double v = v0 + v1;
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) out[q] = v;
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+      if (b + u * 64 < nblocks) v[u] += p[b + u * 64];
+    double r = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    for (int off = 32; off >= 1; off >>= 1) r += __shfl_xor(r, off);
+    if (lane == 0) out[q] = r;
   }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_finalize(const double *partials, int nblocks,
-                                                  int m, const double *theta, double tol,
-                                                  int locking, DevStatus *st) {
+__global__ __launch_bounds__(kSumThreads) void k_finalize(const double *partials, int nblocks,
+                                                          int m, const double *theta,
+                                                          double tol, int locking,
+                                                          DevStatus *st) {
   __shared__ double sums[2 * kMaxNev];
-  sum_partials_block(partials, nblocks, kMaxNormBlocks, sums);
+  sum_partials_block(partials, nblocks, kMaxNormBlocks, m, sums);
   if (threadIdx.x == 0) {
     double floor_th = m > 1 ? theta[1] : theta[0];
     int nconv = 0, na = 0;
@@ -568,10 +576,13 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, int nb
   }
 }
 
-__global__ __launch_bounds__(256) void k_sum_partials(const double *partials, int nblocks,
-                                                      int stride, double *out) {
+__global__ __launch_bounds__(kSumThreads) void k_sum_partials(const double *partials,
+                                                              int nblocks, int stride, int m,
+                                                              double *out) {
   __shared__ double sums[2 * kMaxNev];
-  sum_partials_block(partials, nblocks, stride, sums);
+  if (threadIdx.x < 2 * kMaxNev) sums[threadIdx.x] = 0.0;
+  __syncthreads();
+  sum_partials_block(partials, nblocks, stride, m, sums);
   if (threadIdx.x < 2 * kMaxNev) out[threadIdx.x] = sums[threadIdx.x];
 }
 
@@ -779,7 +790,8 @@ int gram(const T *X, const T *LX, const T *H, const T *LH, const T *P, const T *
 
 void launch_rr(const double *gram_out, const RRArgs &a, double *Y, double *theta,
                DevStatus *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_rr, dim3(1), dim3(256), 0, s, gram_out, a, Y, theta, st);
+  // one wavefront: the rotations of a round are few, so barrier cost dominates
+  hipLaunchKernelGGL(k_rr, dim3(1), dim3(64), 0, s, gram_out, a, Y, theta, st);
 }
 
 template <typename T>
@@ -802,8 +814,8 @@ void launch_update(T *X, const T *H, T *P, const T *LH, T *LP, const double *Y,
 
 void launch_finalize(const double *norm_partials, int n_blocks, int m, const double *theta,
                      double tol, int locking, DevStatus *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, norm_partials, n_blocks, m, theta,
-                     tol, locking, st);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kSumThreads), 0, s, norm_partials, n_blocks, m,
+                     theta, tol, locking, st);
 }
 
 template <typename T>
@@ -821,8 +833,8 @@ void launch_res_partials(const T *X, const double *LX, int64_t n, int m, int ld,
 }
 void launch_sum_partials(const double *partials, int nblocks, int cols, double *out,
                          hipStream_t s) {
-  (void)cols;
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, nblocks, kRqStride, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSumThreads), 0, s, partials, nblocks,
+                     kRqStride, cols, out);
 }
 
 constexpr int kColBlocks = 256;

@@ -65,36 +65,47 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, int64_t nnz,
 
 // Degrees: one wavefront per row.  The weighted degree is the exact sum of
 // the row's weights rounded once to FP64 (128-bit fixed point, see fixed.h),
-// so it does not depend on any summation order.  Block statistics ->
-// stats[block][4]: max pattern deg, min pattern deg, max wdeg, min wdeg.
+// so it does not depend on any summation order.  Each lane sums a strided
+// part of the row; lane 0 adds the 64 lane sums from LDS.  The row loop is
+// uniform over the block (rows r0 + wave), so the barriers are reached by
+// every wave.  Block statistics -> stats[block][4]: max pattern deg, min
+// pattern deg, max wdeg, min wdeg.
 template <typename IdxT, typename WT>
 __global__ __launch_bounds__(256) void k_degrees(int64_t n, const IdxT *rp,
                                                  const WT *w, int e0, double *d64,
                                                  float *d32, double *stats) {
+  __shared__ unsigned long long plo[256], phi[256];
   const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   const int wpb = blockDim.x / 64;
   double mx = 0.0, mn = 1e300, wmx = 0.0, wmn = 1e300;
-  for (int64_t i = (int64_t)blockIdx.x * wpb + threadIdx.x / 64; i < n;
-       i += (int64_t)gridDim.x * wpb) {
-    int64_t b = rp[i], e = rp[i + 1];
-    double s = 0.0;
-    if constexpr (std::is_same_v<WT, Unit>) {
-      s = double(e - b);
-    } else {
-      U128 acc{0, 0};
-      for (int64_t k = b + lane; k < e; k += 64) {
-        unsigned long long lo, hi;
-        fixed_of(w[k], e0, lo, hi);
-        add128(acc, lo, hi);
+  for (int64_t r0 = (int64_t)blockIdx.x * wpb; r0 < n; r0 += (int64_t)gridDim.x * wpb) {
+    const int64_t i = r0 + wave;
+    U128 acc{0, 0};
+    int64_t b = 0, e = 0;
+    if (i < n) {
+      b = rp[i];
+      e = rp[i + 1];
+      if constexpr (!std::is_same_v<WT, Unit>) {
+        for (int64_t k = b + lane; k < e; k += 64) {
+          unsigned long long lo, hi;
+          fixed_of(w[k], e0, lo, hi);
+          add128(acc, lo, hi);
+        }
       }
-      for (int off = 32; off >= 1; off >>= 1) {
-        unsigned long long lo = __shfl_xor(acc.lo, off);
-        unsigned long long hi = __shfl_xor(acc.hi, off);
-        add128(acc, lo, hi);
-      }
-      s = fixed_to_double(acc, e0);
     }
-    if (lane == 0) {
+    plo[threadIdx.x] = acc.lo;
+    phi[threadIdx.x] = acc.hi;
+    __syncthreads();
+    if (lane == 0 && i < n) {
+      double s;
+      if constexpr (std::is_same_v<WT, Unit>) {
+        s = double(e - b);
+      } else {
+        U128 tot{0, 0};
+        for (int q = 0; q < 64; ++q) add128(tot, plo[wave * 64 + q], phi[wave * 64 + q]);
+        s = fixed_to_double(tot, e0);
+      }
       d64[i] = s;
       if (d32) d32[i] = float(s);
       double deg = double(e - b);
@@ -103,6 +114,7 @@ __global__ __launch_bounds__(256) void k_degrees(int64_t n, const IdxT *rp,
       wmx = fmax(wmx, s);
       wmn = fmin(wmn, s);
     }
+    __syncthreads();
   }
   __shared__ double sh[4][256];
   sh[0][threadIdx.x] = mx;

@@ -84,7 +84,8 @@ def test_normalized_eigenpairs_vs_dense(handle, pc, prec):
     nev = 5
     LN = lap.dense_normalized(g.rowptr, g.col, wo)
     lam_ref, Y_ref = eigen.smallest_dense(LN, np.ones(g.n), nev + 1)
-    tol = 1e-9 if prec == sx.FP64 else 1e-5
+    # FP32 vectors: the relative residual floor is near 1e-5 on this graph
+    tol = 1e-9 if prec == sx.FP64 else 1e-4
     opts = sx.Options(problem=sx.NORMALIZED, precond=pc, tol=tol, precision=prec, seed=7,
                       cheb_degree=10, cheb_ratio=30.0, max_iter=5000)
     lam, Y, st = sx.eigensolve(handle, G, nev, opts)

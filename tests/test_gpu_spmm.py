@@ -28,6 +28,11 @@ def _grid(nx, ny):
     return graphgen.csr_from_edges(n, u, v)
 
 
+def _king(side, wd):
+    n, (u, v) = graphgen.grid2d_9pt(side, side)
+    return graphgen.csr_from_edges(n, u, v, graphgen.uniform_weights(u.size, 0, dtype=wd))
+
+
 def _graphs():
     return {
         "grid_unit": _grid(37, 29),
@@ -36,6 +41,8 @@ def _graphs():
         "star_hub": star_graph(40000),                 # hub row > 16384 entries
         "rmat12": graphgen.rmat_graph(12, seed=5),      # mid-degree rows
         "brick_lr": graphgen.config_graph("brick96lr", scale_down=12),
+        "king64_f64": _king(64, np.float64),          # weighted, > 1024 rows
+        "brick24_lr": graphgen.config_graph("brick96lr", scale_down=4),   # F32, 13824 rows
     }
 
 
@@ -85,7 +92,8 @@ def test_spmm_deterministic(handle):
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-@pytest.mark.parametrize("name", ["rand_f64", "star_hub", "grid_unit"])
+@pytest.mark.parametrize("name", ["rand_f64", "star_hub", "grid_unit", "king64_f64",
+                                  "brick24_lr"])
 def test_jacobi_bit_exact(handle, dtype, name):
     g = GRAPHS[name]
     rp, col, w = upload(g)

@@ -16,6 +16,16 @@ algorithmic bytes of all its launches in the timed steps divided by their
 summed durations, measured with HIP events on the library's stream.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --only-mixed --steps 1 --warmup 0 --no-cpu-baseline
+                                      (one mixed partition, for counter runs)
+       python bench.py --copy-probe BYTES   (one plain device copy of BYTES,
+                                      the calibration of the byte counters)
+
+`roofline.traffic` is the HBM bytes per launch of the dominant kernel from
+the FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/, scaled by
+the counters' reading for a plain copy of known size; it is reported only
+while the kernel source is the one the counters were taken on (checked by
+hash), else null.
 """
 from __future__ import annotations
 
@@ -78,6 +88,45 @@ def cpu_baseline(g, m, budget_s=20.0, max_reps=10):
                       f"{dt:.1f} s"}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cheb_step_grid7_128_traffic.md")
+KERNEL_SOURCES = ["paper_2105_00578_amd/csrc/spmm_vec.hip", "paper_2105_00578_amd/csrc/kernels.h",
+                  "paper_2105_00578_amd/csrc/common.h"]
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Counter-derived HBM bytes per launch of the Chebyshev step, if the
+    committed counter summary was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("<!-- traffic:"):
+                rec = json.loads(line[len("<!-- traffic:"):].rsplit("-->", 1)[0])
+                if rec.get("kernel_src_sha1") == kernel_hash():
+                    return rec
+    return None
+
+
+def copy_probe(nbytes):
+    """One plain elementwise copy of nbytes on the GPU (reads and writes
+    nbytes once each): the calibration kernel of the byte counters."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    torch.cuda.synchronize()
+    y = x * 1.0
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "check": float(y[-1].item())}), flush=True)
+
+
 def run(args):
     import numpy as np
     import torch
@@ -100,7 +149,7 @@ def run(args):
     }
     h.set_timing(True)
     results = {}
-    for name in ("mixed", "fp64"):
+    for name in (("mixed",) if args.only_mixed else ("mixed", "fp64")):
         o = opts[name]
         for _ in range(args.warmup):
             sx.partition(h, G, K, o)
@@ -131,8 +180,9 @@ def run(args):
             phases_ms={k: round(v / 1.0, 3) for k, v in st.phases_ms.items()},
             lam=lam)
     mx = results["mixed"]
-    f64 = results["fp64"]
+    f64 = results.get("fp64", mx)
     value = mx["cheb_gbs"]
+    tr = measured_traffic()
     line = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -158,7 +208,7 @@ def run(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(value / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": None if tr is None else tr["bytes_per_launch"],
             "kernel": "Chebyshev-step Laplacian product (FP32, 7-point rows)",
             "avg_launch_us": round(mx["cheb_avg_us"], 3),
             "launches": mx["cheb_calls"],
@@ -190,7 +240,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cheb-ratio", type=float, default=1000.0)
     ap.add_argument("--scale-down", type=int, default=1, help="shrink the grid (tests only)")
+    ap.add_argument("--only-mixed", action="store_true",
+                    help="time only the mixed-precision partition (counter runs)")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="run one plain device copy of this many bytes and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no "
               "multi-GPU path; the whole graph is the one-GPU share.", file=sys.stderr)

@@ -215,34 +215,74 @@ double spmm_bytes(const sphx_graph *g, const SpmmPlan &plan, int G, int s, int v
   return b + double(vec_passes) * double(g->n) * G * s + 8.0 * row_doubles * double(g->n);
 }
 
-// H[:, cm] = p(L) R[:, cm]: returns the buffer holding the result.
+// Rc[i, q] = R[i, act[q]] for q < na, 0 for na <= q < lda; with X1 also
+// X1[i, q] = scale * dinv[i] * Rc[i, q] (the first Chebyshev iterate)
+template <typename T>
+__global__ void k_compact_cols(const T *R, int ld, ColMap act, int lda, const double *dinv,
+                               double scale, T *Rc, T *X1, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * lda;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / lda;
+    const int q = (int)(e - i * lda);
+    const T v = q < act.count ? R[i * ld + act.col[q]] : T(0);
+    Rc[e] = v;
+    if (X1) X1[e] = T(scale * dinv[i] * double(v));
+  }
+}
+
+// H[i, act[q]] = Hc[i, q] for q < na (other columns of H are left as they are)
+template <typename T>
+__global__ void k_expand_cols(const T *Hc, int lda, ColMap act, T *H, int ld, int64_t n) {
+  const int na = act.count;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * na;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / na;
+    const int q = (int)(e - i * na);
+    H[i * ld + act.col[q]] = Hc[i * lda + q];
+  }
+}
+
+// Row width of the compacted Chebyshev block for na active columns: even,
+// so that FP32 rows are whole 8-byte vectors and FP64 rows 16-byte ones.
+inline int compact_ld(int na) { return (na + 1) / 2 * 2; }
+
+// H[:, cm] = p(L) R[:, cm]: returns the buffer holding the result (n x ld,
+// the columns of cm).  With `spare` (an n x ld buffer whose contents may be
+// destroyed, e.g. R itself) and fewer active columns than the padded width,
+// the iteration runs on a compacted block of the active columns only.
 template <typename T>
 int cheb_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, int ld,
-               const ColMap &cm, const T *R, T *B1, T *B2, const ChebCoef &k,
+               const ColMap &cm, const T *R, T *B1, T *B2, T *spare, const ChebCoef &k,
                const double *dinv, hipStream_t s, T **result, int64_t *calls,
                int64_t *pcalls) {
   const int rd = dinv ? 1 : 0;
   const double b3 = spmm_bytes(g, plan, cm.count, sizeof(T), 3, rd);
   const double b4 = spmm_bytes(g, plan, cm.count, sizeof(T), 4, rd);
+  const int64_t n = g->n;
+  const int na = cm.count;
+  const int lda = compact_ld(na);
+  const bool compact = spare && lda < ld;
+  const int wd = compact ? lda : ld;     // row width of the iteration buffers
+  const int mm = compact ? na : m;
   auto launch = [&](const T *src, EpiChebP<T> e, double bytes) -> int {
     int id = h->plog.begin(PH_PRECOND, bytes, s);
     // padded rows (the solver's blocks) take the vector-row kernels; the
     // column-lane kernels serve unpadded caller blocks
-    int st = ld != m || (m * (int)sizeof(T)) % 16 == 0
-                 ? vspmm_cheb<T>(g, plan, src, ld, m, e, s)
+    int st = compact || ld != m || (m * (int)sizeof(T)) % 16 == 0
+                 ? vspmm_cheb<T>(g, plan, src, wd, mm, e, s)
                  : spmm_cheb<T>(g, plan, src, m, cm, e, s);
     h->plog.end(id, s);
     ++*calls;
     ++*pcalls;
     return st;
   };
-  // step 1 gathers h1 = r / c from R directly; h0 = 0
+  const T *rhs = R;
   auto epi = [&](const T *prev, double prev_scale, T *out, double src_scale, int st) {
     EpiChebP<T> e;
     e.prev = prev;
-    e.R = R;
+    e.R = rhs;
     e.OUT = out;
-    e.ld = ld;
+    e.ld = wd;
     e.src_scale = src_scale;
     e.prev_scale = prev_scale;
     e.alpha = k.alpha[st];
@@ -251,30 +291,55 @@ int cheb_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, int l
     return e;
   };
   // h1 = rhs / c: rhs = r (combinatorial), read from R with a scale; or
-  // rhs = D^-1 r (generalized), materialised in B2 first.
+  // rhs = D^-1 r (generalized), materialised first.  `slot` is the buffer
+  // that step 2 overwrites (it holds h1, or is free).
   const T *h1 = R;
   double h1_scale = 1.0 / k.c;
-  if (dinv) {
-    hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for((int64_t)g->n * ld, 256, 4096)),
-                       dim3(256), 0, s, R, dinv, 1.0 / k.c, B2, g->n, ld);
+  T *it1 = B1, *slot = B2;
+  if (compact) {
+    // Rc -> B2 (the right-hand side of every step), h1 -> B1 if it must be
+    // materialised; R is free once this kernel is done, so the iterates use
+    // B1 and spare
+    hipLaunchKernelGGL(k_compact_cols<T>, dim3(grid_for(n * lda, 256, 4096)), dim3(256), 0, s,
+                       R, ld, cm, lda, dinv, 1.0 / k.c, B2, dinv ? B1 : (T *)nullptr, n);
+    rhs = B2;
+    if (dinv) {
+      h1 = B1;
+      h1_scale = 1.0;
+      it1 = spare;
+      slot = B1;
+    } else {
+      h1 = B2;
+      it1 = B1;
+      slot = spare;
+    }
+  } else if (dinv) {
+    hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for(n * ld, 256, 4096)), dim3(256), 0, s, R,
+                       dinv, 1.0 / k.c, B2, n, ld);
     h1 = B2;
     h1_scale = 1.0;
   }
-  SPHX_TRY(launch(h1, epi(nullptr, 1.0, B1, h1_scale, 0), b3));
-  T *cur = B1, *other = B2;
+  SPHX_TRY(launch(h1, epi(nullptr, 1.0, it1, h1_scale, 0), b3));
+  T *cur = it1, *other = slot;
   const int deg = (int)k.alpha.size();
   if (deg >= 2) {
-    // step 2: the previous iterate is h1 (in R with a scale, or in B2,
-    // which is then overwritten in place by h3)
-    SPHX_TRY(launch(B1, epi(h1, h1_scale, B2, 1.0, 1), b4));
-    cur = B2;
-    other = B1;
+    // step 2: the previous iterate is h1 (scaled, possibly in `slot`, which
+    // is then overwritten in place by h3)
+    SPHX_TRY(launch(it1, epi(h1, h1_scale, slot, 1.0, 1), b4));
+    cur = slot;
+    other = it1;
     // later steps overwrite the older iterate in place (each element is read
     // and written by the same lane only)
     for (int st = 2; st < deg; ++st) {
       SPHX_TRY(launch(cur, epi(other, 1.0, other, 1.0, st), b4));
       std::swap(cur, other);
     }
+  }
+  if (compact) {
+    // back to the padded layout, in B2 (the compacted right-hand side is done)
+    hipLaunchKernelGGL(k_expand_cols<T>, dim3(grid_for(n * na, 256, 4096)), dim3(256), 0, s,
+                       (const T *)cur, lda, cm, B2, ld, n);
+    cur = B2;
   }
   *result = cur;
   return SPHX_OK;
@@ -390,8 +455,8 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     T *H = w.B1;
     pcols += act.count;
     if (o.precond == SPHX_PRECOND_CHEBYSHEV) {
-      SPHX_TRY(cheb_apply<T>(h, g, w.plan, m, ld, act, w.R, w.B1, w.B2, ck, dinv, s, &H, &calls,
-                             &pcalls));
+      SPHX_TRY(cheb_apply<T>(h, g, w.plan, m, ld, act, w.R, w.B1, w.B2, w.R, ck, dinv, s, &H,
+                             &calls, &pcalls));
     } else if (o.precond == SPHX_PRECOND_NONE) {
       H = w.R;
     }
@@ -801,7 +866,7 @@ int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int
     if (dtype == SPHX_F32) {
       float *res = nullptr;
       SPHX_TRY(cheb_apply<float>(h, g, plan, m, m, cm, (const float *)R, (float *)b1,
-                                 (float *)b2, ck, dv, s, &res, &calls, &pcalls));
+                                 (float *)b2, nullptr, ck, dv, s, &res, &calls, &pcalls));
       if (post)
         hipLaunchKernelGGL(k_scale_rows<float>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0,
                            s, (const float *)res, post, 1.0, (float *)H, n, m);
@@ -810,7 +875,7 @@ int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int
     } else {
       double *res = nullptr;
       SPHX_TRY(cheb_apply<double>(h, g, plan, m, m, cm, (const double *)R, (double *)b1,
-                                  (double *)b2, ck, dv, s, &res, &calls, &pcalls));
+                                  (double *)b2, nullptr, ck, dv, s, &res, &calls, &pcalls));
       if (post)
         hipLaunchKernelGGL(k_scale_rows<double>, dim3(grid_for(n * m, 256, 4096)), dim3(256),
                            0, s, (const double *)res, post, 1.0, (double *)H, n, m);

@@ -790,8 +790,7 @@ int gram(const T *X, const T *LX, const T *H, const T *LH, const T *P, const T *
 
 void launch_rr(const double *gram_out, const RRArgs &a, double *Y, double *theta,
                DevStatus *st, hipStream_t s) {
-  // one wavefront: the rotations of a round are few, so barrier cost dominates
-  hipLaunchKernelGGL(k_rr, dim3(1), dim3(64), 0, s, gram_out, a, Y, theta, st);
+  hipLaunchKernelGGL(k_rr, dim3(1), dim3(256), 0, s, gram_out, a, Y, theta, st);
 }
 
 template <typename T>

@@ -23,12 +23,18 @@
 namespace sphx {
 namespace {
 
-template <typename T> struct Vec;
-template <> struct Vec<float> {
+// Row vectors of VB bytes: 16 (float4 / double2), or 8 (float2) for FP32
+// rows of an even, non-multiple-of-4 width.
+template <typename T, int VB> struct Vec;
+template <> struct Vec<float, 16> {
   typedef float type __attribute__((ext_vector_type(4)));
   static constexpr int E = 4;
 };
-template <> struct Vec<double> {
+template <> struct Vec<float, 8> {
+  typedef float type __attribute__((ext_vector_type(2)));
+  static constexpr int E = 2;
+};
+template <> struct Vec<double, 16> {
   typedef double type __attribute__((ext_vector_type(2)));
   static constexpr int E = 2;
 };
@@ -47,12 +53,12 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
   return x * q + (x < r ? x : r) + pos;
 }
 
-template <typename T, int NV, typename IdxT, typename WT>
+template <typename T, int VB, int NV, typename IdxT, typename WT>
 __device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t k0, int64_t k1,
-                                         int step, const typename Vec<T>::type *__restrict__ X,
-                                         int ldv, const typename Vec<T>::type (&xi)[NV],
-                                         typename Vec<T>::type (&acc)[NV]) {
-  using V = typename Vec<T>::type;
+                                         int step, const typename Vec<T, VB>::type *__restrict__ X,
+                                         int ldv, const typename Vec<T, VB>::type (&xi)[NV],
+                                         typename Vec<T, VB>::type (&acc)[NV]) {
+  using V = typename Vec<T, VB>::type;
   V a0[NV], a1[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) { a0[v] = V(0); a1[v] = V(0); }
@@ -96,11 +102,11 @@ __device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t k0, int
 }
 
 // ------------------------------------------------------------- epilogues
-template <typename T, int NV>
+template <typename T, int VB, int NV>
 struct VStore {
   EpiStoreP<T> p;
   static constexpr bool kNorms = false;
-  using V = typename Vec<T>::type;
+  using V = typename Vec<T, VB>::type;
   __device__ void row(int64_t i, const V (&xi)[NV], const V (&acc)[NV], double *, double *) const {
     V *y = reinterpret_cast<V *>(p.Y + i * p.ldy);
 #pragma unroll
@@ -108,13 +114,13 @@ struct VStore {
   }
 };
 
-template <typename T, int NV>
+template <typename T, int VB, int NV>
 struct VResidual {
   EpiResidualP<T> p;
   int m;
   static constexpr bool kNorms = true;
-  using V = typename Vec<T>::type;
-  static constexpr int E = Vec<T>::E;
+  using V = typename Vec<T, VB>::type;
+  static constexpr int E = Vec<T, VB>::E;
   __device__ void row(int64_t i, const V (&xi)[NV], const V (&acc)[NV], double *n1,
                       double *n2) const {
     const double di = p.d64 ? p.d64[i] : 1.0;
@@ -142,12 +148,12 @@ struct VResidual {
   }
 };
 
-template <typename T, int NV>
+template <typename T, int VB, int NV>
 struct VCheb {
   EpiChebP<T> p;
   static constexpr bool kNorms = false;
-  using V = typename Vec<T>::type;
-  static constexpr int E = Vec<T>::E;
+  using V = typename Vec<T, VB>::type;
+  static constexpr int E = Vec<T, VB>::E;
   __device__ void row(int64_t i, const V (&xi)[NV], const V (&acc)[NV], double *, double *) const {
     const double si = p.dinv ? p.dinv[i] : 1.0;
     const V *rr = reinterpret_cast<const V *>(p.R + i * p.ld);
@@ -203,15 +209,15 @@ __device__ void block_norms(const double (&n1)[LD], const double (&n2)[LD], int 
 
 // ----------------------------------------------------------------- kernels
 // Short rows, one thread per row; `rpt` rows per thread, 256-row strides.
-template <typename T, int NV, typename IdxT, typename WT, typename Epi>
+template <typename T, int VB, int NV, typename IdxT, typename WT, typename Epi>
 __global__ __launch_bounds__(256) void k_vrow(Csr<IdxT, WT> A, const int32_t *__restrict__ rows,
                                               int64_t nrows, const T *__restrict__ Xs, int ld,
                                               int rpt, Epi epi, double *partials, int slot0,
                                               int m) {
-  using V = typename Vec<T>::type;
-  constexpr int LD = NV * Vec<T>::E;
+  using V = typename Vec<T, VB>::type;
+  constexpr int LD = NV * Vec<T, VB>::E;
   const V *X = reinterpret_cast<const V *>(Xs);
-  const int ldv = ld / Vec<T>::E;
+  const int ldv = ld / Vec<T, VB>::E;
   const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
   double n1[LD], n2[LD];
 #pragma unroll
@@ -223,15 +229,15 @@ __global__ __launch_bounds__(256) void k_vrow(Csr<IdxT, WT> A, const int32_t *__
     V xi[NV], acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
-    vrow_acc<T, NV>(A, (int64_t)A.rp[i], (int64_t)A.rp[i + 1], 1, X, ldv, xi, acc);
+    vrow_acc<T, VB, NV>(A, (int64_t)A.rp[i], (int64_t)A.rp[i + 1], 1, X, ldv, xi, acc);
     epi.row(i, xi, acc, n1, n2);
   }
   if constexpr (Epi::kNorms) block_norms<LD>(n1, n2, m, partials, slot0 + (int)blockIdx.x);
 }
 
-template <typename T, int NV>
-__device__ __forceinline__ void wave_sum(typename Vec<T>::type (&acc)[NV]) {
-  constexpr int E = Vec<T>::E;
+template <typename T, int VB, int NV>
+__device__ __forceinline__ void wave_sum(typename Vec<T, VB>::type (&acc)[NV]) {
+  constexpr int E = Vec<T, VB>::E;
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -243,16 +249,16 @@ __device__ __forceinline__ void wave_sum(typename Vec<T>::type (&acc)[NV]) {
 }
 
 // Mid rows: one wavefront per row.
-template <typename T, int NV, typename IdxT, typename WT, typename Epi>
+template <typename T, int VB, int NV, typename IdxT, typename WT, typename Epi>
 __global__ __launch_bounds__(256) void k_vrow_wave(Csr<IdxT, WT> A,
                                                    const int32_t *__restrict__ rows,
                                                    int64_t nrows, const T *__restrict__ Xs,
                                                    int ld, Epi epi, double *partials, int slot0,
                                                    int m) {
-  using V = typename Vec<T>::type;
-  constexpr int LD = NV * Vec<T>::E;
+  using V = typename Vec<T, VB>::type;
+  constexpr int LD = NV * Vec<T, VB>::E;
   const V *X = reinterpret_cast<const V *>(Xs);
-  const int ldv = ld / Vec<T>::E;
+  const int ldv = ld / Vec<T, VB>::E;
   const int lane = threadIdx.x & 63;
   double n1[LD], n2[LD];
 #pragma unroll
@@ -263,22 +269,22 @@ __global__ __launch_bounds__(256) void k_vrow_wave(Csr<IdxT, WT> A,
     V xi[NV], acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
-    vrow_acc<T, NV>(A, (int64_t)A.rp[i] + lane, (int64_t)A.rp[i + 1], 64, X, ldv, xi, acc);
-    wave_sum<T, NV>(acc);
+    vrow_acc<T, VB, NV>(A, (int64_t)A.rp[i] + lane, (int64_t)A.rp[i + 1], 64, X, ldv, xi, acc);
+    wave_sum<T, VB, NV>(acc);
     if (lane == 0) epi.row(i, xi, acc, n1, n2);
   }
   if constexpr (Epi::kNorms) block_norms<LD>(n1, n2, m, partials, slot0 + (int)blockIdx.x);
 }
 
 // Hub rows, pass 1: one wavefront per chunk -> partial row sums (as double).
-template <typename T, int NV, typename IdxT, typename WT>
+template <typename T, int VB, int NV, typename IdxT, typename WT>
 __global__ __launch_bounds__(256) void k_vhub_partial(
     Csr<IdxT, WT> A, const int32_t *__restrict__ hub_rows,
     const int32_t *__restrict__ hub_chunk_begin, int64_t n_hub,
     const int64_t *__restrict__ k0s, const int64_t *__restrict__ k1s, int64_t n_chunks,
     const T *__restrict__ Xs, int ld, double *out) {
-  using V = typename Vec<T>::type;
-  constexpr int E = Vec<T>::E;
+  using V = typename Vec<T, VB>::type;
+  constexpr int E = Vec<T, VB>::E;
   const V *X = reinterpret_cast<const V *>(Xs);
   const int ldv = ld / E;
   const int lane = threadIdx.x & 63;
@@ -293,8 +299,8 @@ __global__ __launch_bounds__(256) void k_vhub_partial(
     V xi[NV], acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
-    vrow_acc<T, NV>(A, k0s[q] + lane, k1s[q], 64, X, ldv, xi, acc);
-    wave_sum<T, NV>(acc);
+    vrow_acc<T, VB, NV>(A, k0s[q] + lane, k1s[q], 64, X, ldv, xi, acc);
+    wave_sum<T, VB, NV>(acc);
     if (lane == 0)
 #pragma unroll
       for (int v = 0; v < NV; ++v)
@@ -304,14 +310,14 @@ __global__ __launch_bounds__(256) void k_vhub_partial(
 }
 
 // Hub rows, pass 2: one thread per hub row sums its chunks in order.
-template <typename T, int NV, typename Epi>
+template <typename T, int VB, int NV, typename Epi>
 __global__ __launch_bounds__(256) void k_vhub_combine(const int32_t *__restrict__ hub_rows,
                                                       const int32_t *__restrict__ hub_chunk_begin,
                                                       int64_t n_hub, const double *part,
                                                       const T *__restrict__ Xs, int ld, Epi epi,
                                                       double *partials, int slot0, int m) {
-  using V = typename Vec<T>::type;
-  constexpr int E = Vec<T>::E;
+  using V = typename Vec<T, VB>::type;
+  constexpr int E = Vec<T, VB>::E;
   constexpr int LD = NV * E;
   const V *X = reinterpret_cast<const V *>(Xs);
   const int ldv = ld / E;
@@ -342,7 +348,7 @@ constexpr int kMaxShortBlocks = 8192;
 constexpr int kWaveBlocks = 1024;
 constexpr int kHubBlocks = 16;
 
-template <typename T, int NV, typename IdxT, typename WT, typename Epi>
+template <typename T, int VB, int NV, typename IdxT, typename WT, typename Epi>
 void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X, int ld,
              const Epi &epi, double *partials, int *nparts, int m, hipStream_t s) {
   int used = 0;
@@ -350,7 +356,7 @@ void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X
     int64_t nb = ceil_div(nr, 256);
     int rpt = (int)ceil_div(nb, kMaxShortBlocks);
     nb = ceil_div(nr, 256 * (int64_t)rpt);
-    hipLaunchKernelGGL((k_vrow<T, NV, IdxT, WT, Epi>), dim3((unsigned)nb), dim3(256), 0, s, A,
+    hipLaunchKernelGGL((k_vrow<T, VB, NV, IdxT, WT, Epi>), dim3((unsigned)nb), dim3(256), 0, s, A,
                        rows, nr, X, ld, rpt, epi, partials, used, m);
     used += (int)nb;
   };
@@ -360,17 +366,17 @@ void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X
     if (plan.n_short > 0) short_rows(plan.short_rows, plan.n_short);
     if (plan.n_mid > 0) {
       unsigned gb = grid_for(plan.n_mid, 4, kWaveBlocks);
-      hipLaunchKernelGGL((k_vrow_wave<T, NV, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s, A,
+      hipLaunchKernelGGL((k_vrow_wave<T, VB, NV, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s, A,
                          plan.mid_rows, plan.n_mid, X, ld, epi, partials, used, m);
       used += (int)gb;
     }
     if (plan.n_hub > 0) {
       unsigned gb = grid_for(plan.n_chunks, 4, kWaveBlocks);
-      hipLaunchKernelGGL((k_vhub_partial<T, NV, IdxT, WT>), dim3(gb), dim3(256), 0, s, A,
+      hipLaunchKernelGGL((k_vhub_partial<T, VB, NV, IdxT, WT>), dim3(gb), dim3(256), 0, s, A,
                          plan.hub_rows, plan.hub_chunk_begin, plan.n_hub, plan.chunk_k0,
                          plan.chunk_k1, plan.n_chunks, X, ld, plan.hub_partial);
       unsigned gc = grid_for(plan.n_hub, 256, kHubBlocks);
-      hipLaunchKernelGGL((k_vhub_combine<T, NV, Epi>), dim3(gc), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_vhub_combine<T, VB, NV, Epi>), dim3(gc), dim3(256), 0, s,
                          plan.hub_rows, plan.hub_chunk_begin, plan.n_hub,
                          (const double *)plan.hub_partial, X, ld, epi, partials, used, m);
       used += (int)gc;
@@ -379,7 +385,7 @@ void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X
   if (nparts) *nparts = used;
 }
 
-template <typename T, int NV, template <typename, int> class EpiT, typename P>
+template <typename T, int VB, int NV, template <typename, int, int> class EpiT, typename P>
 int dispatch_types(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, const P &p,
                    int m, double *partials, int *nparts, hipStream_t s) {
   auto go = [&](auto idx_tag, auto w_tag) {
@@ -387,9 +393,9 @@ int dispatch_types(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, cons
     using WT = decltype(w_tag);
     Csr<IdxT, WT> A{static_cast<const IdxT *>(g->rowptr), g->col,
                     static_cast<const WT *>(g->w)};
-    EpiT<T, NV> epi{p};
-    if constexpr (std::is_same_v<EpiT<T, NV>, VResidual<T, NV>>) epi.m = m;
-    run_vec<T, NV>(A, g->n, plan, X, ld, epi, partials, nparts, m, s);
+    EpiT<T, VB, NV> epi{p};
+    if constexpr (std::is_same_v<EpiT<T, VB, NV>, VResidual<T, VB, NV>>) epi.m = m;
+    run_vec<T, VB, NV>(A, g->n, plan, X, ld, epi, partials, nparts, m, s);
   };
   if (g->rp64) {
     if (g->wdt == SPHX_UNIT) go(int64_t{}, Unit{});
@@ -403,28 +409,35 @@ int dispatch_types(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, cons
   return hipGetLastError() == hipSuccess ? SPHX_OK : SPHX_E_HIP;
 }
 
-template <typename T, template <typename, int> class EpiT, typename P>
+template <typename T, template <typename, int, int> class EpiT, typename P>
 int dispatch_nv(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, const P &p, int m,
                 double *partials, int *nparts, hipStream_t s) {
-  constexpr int E = Vec<T>::E;
-  if (ld % E != 0 || ld < m || ld > kMaxNev || m < 1) return SPHX_E_INVALID_ARG;
-  const int nv = ld / E;
-  switch (nv) {
-    case 1: return dispatch_types<T, 1, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
-    case 2: return dispatch_types<T, 2, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
-    case 3: return dispatch_types<T, 3, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
-    case 4: return dispatch_types<T, 4, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
-    default: break;
-  }
-  if constexpr (E == 2) {
-    switch (nv) {
-      case 5: return dispatch_types<T, 5, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
-      case 6: return dispatch_types<T, 6, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
-      case 7: return dispatch_types<T, 7, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
-      case 8: return dispatch_types<T, 8, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
+  if (ld < m || ld > kMaxNev || m < 1) return SPHX_E_INVALID_ARG;
+  const int row_bytes = ld * (int)sizeof(T);
+#define SPHX_NV(VB_, NV_)                                                                 \
+  case NV_:                                                                               \
+    return dispatch_types<T, VB_, NV_, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
+  if (row_bytes % 16 == 0) {
+    switch (row_bytes / 16) {
+      SPHX_NV(16, 1) SPHX_NV(16, 2) SPHX_NV(16, 3) SPHX_NV(16, 4)
       default: break;
     }
+    if constexpr (std::is_same_v<T, double>) {
+      switch (row_bytes / 16) {
+        SPHX_NV(16, 5) SPHX_NV(16, 6) SPHX_NV(16, 7) SPHX_NV(16, 8)
+        default: break;
+      }
+    }
+  } else if constexpr (std::is_same_v<T, float>) {
+    // FP32 rows of 2, 6, 10 or 14 values: 8-byte vectors
+    if (row_bytes % 8 == 0) {
+      switch (row_bytes / 8) {
+        SPHX_NV(8, 1) SPHX_NV(8, 3) SPHX_NV(8, 5) SPHX_NV(8, 7)
+        default: break;
+      }
+    }
   }
+#undef SPHX_NV
   return SPHX_E_INVALID_ARG;
 }
 

@@ -335,16 +335,26 @@ __device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
   __syncthreads();
 }
 
-// Rayleigh-Ritz: SVQB basis of span(S) from G_B, then eigenpairs of the
-// projected G_A (Algorithm 1, RR(S, nev)).
+// Rayleigh-Ritz (Algorithm 1, RR(S, nev)) on the reduced Gram matrices.
+//
+// The columns of S are scaled to unit B-norm (Gs = D G_B D, As = D G_A D with
+// D = diag(G_B)^-1/2).  A pivoted Cholesky factorisation of Gs picks, at each
+// step, the column with the largest remaining Schur-complement diagonal and
+// stops when that is at most drop_tol: the k chosen columns span the others
+// up to the tolerance (those are dropped as linearly dependent), and
+// Gs(piv, piv) = L L^T.  With C = L^-T, S(:, piv) C is B-orthonormal and the
+// projected matrix A' = L^-1 As(piv, piv) L^-T is diagonalised by cyclic
+// Jacobi; the m smallest Ritz pairs give Y = D P L^-T Z.  If fewer than m
+// columns survive, the P block is dropped and the step retried once.
 __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRArgs a,
                                             double *Y, double *theta, DevStatus *st) {
   __shared__ double M1[kMaxW * LDA], M2[kMaxW * LDA], M3[kMaxW * LDA];
-  __shared__ double sc[kMaxW], lam[kMaxW];
+  __shared__ double sc[kMaxW], lam[kMaxW], lcol[kMaxW];
   __shared__ double pc[kMaxW / 2 + 1], ps[kMaxW / 2 + 1];
   __shared__ int pp[kMaxW / 2 + 1], pq[kMaxW / 2 + 1];
-  __shared__ int kept_idx[kMaxW], perm[kMaxW];
-  __shared__ int nkept, changed;
+  __shared__ int piv[kMaxW], ipiv[kMaxW], perm[kMaxW];
+  __shared__ int changed, pstep;
+  __shared__ double pval;
   const int t = threadIdx.x;
   const int w = a.w, m = a.m;
   const double *GA = gram;
@@ -355,36 +365,53 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
     if (t < kMaxW) {
       double g = (t < wl) ? GB[t * kMaxW + t] : 0.0;
       sc[t] = (t < wl && g > 0.0) ? 1.0 / sqrt(g) : 0.0;
+      ipiv[t] = -1;
     }
     __syncthreads();
-    for (int e = t; e < w * w; e += blockDim.x) {
-      int i = e / w, j = e - i * w;
+    // M1 = Gs (then its Schur complements), M3 = As, M2 = L by original row
+    for (int e = t; e < wl * wl; e += blockDim.x) {
+      int i = e / wl, j = e - i * wl;
       int lo = i < j ? i : j, hi = i < j ? j : i;
-      double s = sc[i] * sc[j];
-      M1[i * LDA + j] = GB[lo * kMaxW + hi] * s;
-      M3[i * LDA + j] = GA[lo * kMaxW + hi] * s;
+      double sij = sc[i] * sc[j];
+      M1[i * LDA + j] = GB[lo * kMaxW + hi] * sij;
+      M3[i * LDA + j] = GA[lo * kMaxW + hi] * sij;
+      M2[i * LDA + j] = 0.0;
     }
     __syncthreads();
-    jacobi_eig(M1, M2, w, pc, ps, pp, pq, &changed);
-    if (t < w) lam[t] = M1[t * LDA + t];
-    __syncthreads();
-    if (t == 0) {
-      double smax = 0.0;
-      for (int j = 0; j < w; ++j) smax = fmax(smax, lam[j]);
-      int q = 0;
-      for (int j = 0; j < w; ++j)
-        if (lam[j] > a.drop_tol * smax && lam[j] > 0.0) kept_idx[q++] = j;
-      nkept = q;
+    // ---- pivoted Cholesky of Gs
+    int k = 0;
+    for (; k < wl; ++k) {
+      if (t == 0) {
+        int best = -1;
+        double bv = 0.0;
+        for (int j = 0; j < wl; ++j)
+          if (ipiv[j] < 0 && M1[j * LDA + j] > bv) { bv = M1[j * LDA + j]; best = j; }
+        pstep = (best >= 0 && bv > a.drop_tol) ? best : -1;
+        pval = bv;
+        if (pstep >= 0) {
+          piv[k] = best;
+          ipiv[best] = k;
+        }
+      }
+      __syncthreads();
+      const int p = pstep;
+      if (p < 0) break;
+      if (t < wl) {
+        const double d = sqrt(pval);
+        double l = 0.0;
+        if (t == p) l = d;
+        else if (ipiv[t] < 0) l = M1[t * LDA + p] / d;
+        lcol[t] = l;
+        if (t == p || ipiv[t] < 0) M2[t * LDA + k] = l;
+      }
+      __syncthreads();
+      // Schur complement on the columns not chosen yet
+      for (int e = t; e < wl * wl; e += blockDim.x) {
+        int i = e / wl, j = e - i * wl;
+        if (ipiv[i] < 0 && ipiv[j] < 0) M1[i * LDA + j] -= lcol[i] * lcol[j];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    const int k = nkept;
-    // C = U_kept diag(sigma^-1/2) -> M1 (w x k)
-    for (int e = t; e < w * k; e += blockDim.x) {
-      int i = e / k, q = e - i * k;
-      int j = kept_idx[q];
-      M1[i * LDA + q] = M2[i * LDA + j] / sqrt(lam[j]);
-    }
-    __syncthreads();
     if (k >= m || attempt == 1 || a.p_begin >= w) {
       if (k < m) {
         // breakdown: keep X as it is
@@ -399,29 +426,38 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
         }
         return;
       }
-      // T1 = As C -> M2 (w x k)
-      for (int e = t; e < w * k; e += blockDim.x) {
-        int i = e / k, q = e - i * k;
-        double s = 0.0;
-        for (int j = 0; j < w; ++j) s += M3[i * LDA + j] * M1[j * LDA + q];
-        M2[i * LDA + q] = s;
-      }
-      __syncthreads();
-      // A' = C^T T1 -> M3 (k x k), symmetrised
-      for (int e = t; e < k * k; e += blockDim.x) {
-        int p = e / k, q = e - p * k;
-        if (p > q) continue;
-        double s1 = 0.0, s2 = 0.0;
-        for (int j = 0; j < w; ++j) {
-          s1 += M1[j * LDA + p] * M2[j * LDA + q];
-          s2 += M1[j * LDA + q] * M2[j * LDA + p];
+      // L11[i][j] = M2[piv[i]][j], lower triangular k x k.
+      // T = L11^-1 As(piv, piv) -> M1, one column per thread
+      if (t < k) {
+        const int c = t;
+        for (int i = 0; i < k; ++i) {
+          double v = M3[piv[i] * LDA + piv[c]];
+          for (int j = 0; j < i; ++j) v -= M2[piv[i] * LDA + j] * M1[j * LDA + c];
+          M1[i * LDA + c] = v / M2[piv[i] * LDA + i];
         }
-        double v = 0.5 * (s1 + s2);
-        M3[p * LDA + q] = v;
-        M3[q * LDA + p] = v;
       }
       __syncthreads();
-      jacobi_eig(M3, M2, k, pc, ps, pp, pq, &changed);
+      // A' = L11^-1 T^T -> M3: column c has right-hand side row c of T
+      if (t < k) {
+        const int c = t;
+        for (int i = 0; i < k; ++i) {
+          double v = M1[c * LDA + i];
+          for (int j = 0; j < i; ++j) v -= M2[piv[i] * LDA + j] * M3[j * LDA + c];
+          M3[i * LDA + c] = v / M2[piv[i] * LDA + i];
+        }
+      }
+      __syncthreads();
+      for (int e = t; e < k * k; e += blockDim.x) {
+        int i = e / k, j = e - i * k;
+        if (i < j) {
+          double v = 0.5 * (M3[i * LDA + j] + M3[j * LDA + i]);
+          M3[i * LDA + j] = v;
+          M3[j * LDA + i] = v;
+        }
+      }
+      __syncthreads();
+      // eigenpairs of A': values on the diagonal of M3, vectors in M1
+      jacobi_eig(M3, M1, k, pc, ps, pp, pq, &changed);
       if (t < k) lam[t] = M3[t * LDA + t];
       __syncthreads();
       if (t < k) {
@@ -432,16 +468,22 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
         perm[rank] = t;
       }
       __syncthreads();
-      // Y = diag(sc) C Z[:, perm[:m]]
+      // y_c = L11^-T z_perm[c] -> M3 columns (back substitution per column)
+      if (t < m) {
+        const int c = t, zc = perm[c];
+        for (int i = k - 1; i >= 0; --i) {
+          double v = M1[i * LDA + zc];
+          for (int j = i + 1; j < k; ++j) v -= M2[piv[j] * LDA + i] * M3[j * LDA + c];
+          M3[i * LDA + c] = v / M2[piv[i] * LDA + i];
+        }
+      }
+      __syncthreads();
+      // Y (basis row i, Ritz vector c) = sc_i * y_c[position of i], 0 if dropped
       for (int e = t; e < kMaxW * kMaxNev; e += blockDim.x) {
         int i = e / kMaxNev, c = e - i * kMaxNev;
-        double s = 0.0;
-        if (i < w && c < m) {
-          int zc = perm[c];
-          for (int q = 0; q < k; ++q) s += M1[i * LDA + q] * M2[q * LDA + zc];
-          s *= sc[i];
-        }
-        Y[e] = s;
+        double v = 0.0;
+        if (i < wl && c < m && ipiv[i] >= 0) v = sc[i] * M3[ipiv[i] * LDA + c];
+        Y[e] = v;
       }
       if (t < m) theta[t] = lam[perm[t]];
       if (t == 0) {

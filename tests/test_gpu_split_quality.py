@@ -117,5 +117,7 @@ def test_partition_end_to_end_grid64(handle, prec):
     c_ref, _ = quality.cutsize(g.rowptr, g.col, None, p_ref)
     assert cut == c_ref
     assert imb == quality.imbalance(p_ref, 4) == 1.0
-    # a good spectral split of the grid: close to the straight quadrant cut
-    assert cut <= 1.6 * 128
+    # lambda_1 = lambda_2 on the square grid, so any rotation of the pair is a
+    # valid embedding: axis-aligned coordinates give the quadrant cut (128),
+    # the 45-degree rotation two staircase cuts (about 256)
+    assert cut <= 2.1 * 128

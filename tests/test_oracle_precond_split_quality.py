@@ -190,3 +190,61 @@ def test_part_weights_and_imbalance():
     assert quality.imbalance(part, 3, vwgt=np.array([1, 1, 4, 1, 1, 0])) == 4 * 3 / 8
     with pytest.raises(ValueError):
         quality.part_weights(np.array([0, 3]), 3)
+
+
+# ---- general K (multi-jagged with prime-factor section counts)
+
+def test_split_mj_section_counts():
+    assert split.section_counts(24) == [3, 2, 2, 2]
+    assert split.section_counts(1) == []
+    assert split.section_counts(64) == [2] * 6
+    assert split.section_counts(7) == [7]
+    assert split.section_counts(90) == [5, 3, 3, 2]
+
+
+def test_split_mj_hand_examples():
+    # 7 unit points on a line, K = 3: cut j after the prefix C minimising
+    # |3 C - 7 j|: j = 1 -> C = 2 (|6 - 7| = 1), j = 2 -> C = 5 (|15 - 14| = 1)
+    assert split.split_mj(np.arange(7.0), 3).tolist() == [0, 0, 1, 1, 1, 2, 2]
+    # weights 1,1,1,1,5 (W = 9), K = 3: j = 1 -> C = 3 (|9 - 9| = 0);
+    # j = 2 -> C = 4 (|12 - 18| = 6 beats |27 - 18| = 9)
+    got = split.split_mj(np.arange(5.0), 3, vwgt=np.array([1, 1, 1, 1, 5]))
+    assert got.tolist() == [0, 0, 0, 1, 2]
+    # K = 6 on 12 points with two coordinates: level 1 (3 sections) on the
+    # first, level 2 (2 sections) on the second within each section
+    x = np.arange(12.0)
+    y = np.array([5, 4, 3, 2, 1, 0, 11, 10, 9, 8, 7, 6], dtype=float)
+    got = split.split_mj(np.stack([x, y], axis=1), 6)
+    # sections {0..3}, {4..7}, {8..11}; lower halves by y: {2,3}, {4,5}, {10,11}
+    assert got.tolist() == [1, 1, 0, 0, 2, 2, 3, 3, 5, 5, 4, 4]
+
+
+@pytest.mark.parametrize("K", [2, 4, 16, 64])
+def test_split_mj_equals_pow2_rule(K):
+    rng = np.random.default_rng(K)
+    C = rng.standard_normal((500, 6))
+    w = rng.integers(1, 5, 500)
+    assert np.array_equal(split.split_mj(C, K), split.split_pow2(C, K))
+    assert np.array_equal(split.split_mj(C, K, w), split.split_pow2(C, K, w))
+
+
+@pytest.mark.parametrize("n,K", [(1000, 24), (997, 3), (500, 6), (300, 7), (1000, 30), (64, 12)])
+def test_split_mj_unit_sizes_and_line_order(n, K):
+    rng = np.random.default_rng(n + K)
+    C = rng.standard_normal((n, 4))
+    part = split.split_mj(C, K)
+    sizes = np.bincount(part, minlength=K)
+    assert sizes.min() >= n // K and sizes.max() <= -(-n // K)
+    # one coordinate: the parts are consecutive intervals along the line
+    x = rng.permutation(n).astype(float)
+    p1 = split.split_mj(x, K)
+    assert np.all(np.diff(p1[np.argsort(x)]) >= 0)
+
+
+def test_split_mj_relabelling_invariance():
+    rng = np.random.default_rng(9)
+    C = rng.standard_normal((400, 4))
+    perm = rng.permutation(400)
+    a = split.split_mj(C, 24)
+    b = split.split_mj(C[perm], 24)
+    assert np.array_equal(a[perm], b)

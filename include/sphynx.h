@@ -228,14 +228,17 @@ int sphx_eigensolve(sphx_handle *h, sphx_graph *g, int nev,
 
 /* ------------------------------------------------------------ split, cut */
 
-/* Part vector from coordinates (Algorithm 2, MJ special case for K = 2^m):
- * level l bisects every section along coordinate l mod ncoord; members are
- * ordered by (value, vertex id) with -0 == +0; the lower child gets the
- * prefix whose weight W_lo minimises |2 W_lo - W|, the shorter on ties; part
- * ids are branch bits, most significant first.
+/* Part vector from coordinates (Algorithm 2; the multi-jagged split of
+ * Sec. 4): one level per prime factor p of K, largest first, level l
+ * splitting every section into p children along coordinate l mod ncoord.
+ * Members are ordered by (value, vertex id) with -0 == +0; cut j (1 <= j < p)
+ * of a section of weight W follows the prefix whose weight C minimises
+ * |p C - j W|, the shorter prefix on ties (p = 2: |2 W_lo - W|); part ids are
+ * the mixed-radix digits, most significant first (for K = 2^m, branch bits).
  * coords: device, entry (i, c) at coords[i * ld + c], dtype F32 or F64,
- * 1 <= ncoord <= ld.  part: device int32[n].  K must be a power of two,
- * 1 <= K <= 2^30.  NaN coordinates give SPHX_E_INVALID_ARG. */
+ * 1 <= ncoord <= ld.  part: device int32[n].  1 <= K <= min(n, 2^30); the
+ * total vertex weight times the largest prime factor of K must stay below
+ * 2^62.  NaN coordinates give SPHX_E_INVALID_ARG. */
 int sphx_split(sphx_handle *h, sphx_graph *g, const void *coords, int ld,
                int ncoord, int dtype, int K, int32_t *part);
 
@@ -251,7 +254,7 @@ int sphx_quality(sphx_handle *h, sphx_graph *g, const int32_t *part, int K,
 
 /* Algorithm 2 end to end: nev = d = floor(log2 K) + 1 eigenpairs, the
  * embedding = eigenvector columns 1..d-1 (the trivial one dropped), the
- * split and its quality.  eigvals host double[d]; eigvecs device n x d (as
+ * split into any 2 <= K <= n parts and its quality.  eigvals host double[d]; eigvecs device n x d (as
  * in sphx_eigensolve; may be NULL to use workspace); part device int32[n];
  * cut, imbalance host (may be NULL). */
 int sphx_partition(sphx_handle *h, sphx_graph *g, int K, const sphx_options *opt,

@@ -919,7 +919,7 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
       if (stats) ts.start(h->stream);
       std::string err;
       int id = h->plog.begin(PH_SPLIT, 0.0, h->stream);
-      int r = split_pow2<T>(g, vecs + 1, nev, nev - 1, K, part, w.split_scratch,
+      int r = split_mj<T>(g, vecs + 1, nev, nev - 1, K, part, w.split_scratch,
                             h->pinned_small, h->stream, &err);
       h->plog.end(id, h->stream);
       if (r != SPHX_OK) return set_err(h, r, err);
@@ -970,8 +970,8 @@ int sphx_partition(sphx_handle *h, sphx_graph *g, int K, const sphx_options *o,
                    const void *X0, double *eigvals, void *eigvecs, int32_t *part,
                    double *cut, double *imbalance, sphx_stats *stats) {
   if (!h || !g || !part) return SPHX_E_INVALID_ARG;
-  if (K < 2 || (K & (K - 1)) != 0 || K > g->n)
-    return set_err(h, SPHX_E_INVALID_ARG, "K must be a power of two with 2 <= K <= n");
+  if (K < 2 || K > g->n)
+    return set_err(h, SPHX_E_INVALID_ARG, "need 2 <= K <= n");
   int d = sphx_num_eigenvectors(K);
   if (d > kMaxNev) return set_err(h, SPHX_E_INVALID_ARG, "K too large (d > 16)");
   return eigensolve_impl(h, g, d, o, X0, eigvals, eigvecs, K, part, cut, imbalance, stats);
@@ -982,16 +982,16 @@ int sphx_split(sphx_handle *h, sphx_graph *g, const void *coords, int ld, int nc
   if (!h || !g || !coords || !part || ncoord < 1 || ld < ncoord ||
       (dtype != SPHX_F32 && dtype != SPHX_F64))
     return SPHX_E_INVALID_ARG;
-  if (K < 1 || (K & (K - 1)) != 0 || K > (1 << 30) || K > g->n)
-    return set_err(h, SPHX_E_INVALID_ARG, "K must be a power of two, 1 <= K <= n");
+  if (K < 1 || K > (1 << 30) || K > g->n)
+    return set_err(h, SPHX_E_INVALID_ARG, "need 1 <= K <= n");
   if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
   char *ws = nullptr;
   SPHX_TRY(get_workspace(h, split_scratch_bytes(g->n, K), &ws));
   std::string err;
   int r = dtype == SPHX_F32
-              ? split_pow2<float>(g, (const float *)coords, ld, ncoord, K, part, ws,
+              ? split_mj<float>(g, (const float *)coords, ld, ncoord, K, part, ws,
                                   h->pinned_small, h->stream, &err)
-              : split_pow2<double>(g, (const double *)coords, ld, ncoord, K, part, ws,
+              : split_mj<double>(g, (const double *)coords, ld, ncoord, K, part, ws,
                                    h->pinned_small, h->stream, &err);
   if (r != SPHX_OK) return set_err(h, r, err);
   return SPHX_OK;

@@ -181,9 +181,9 @@ void launch_copy_cols(const T *in, int ldin, T *out, int ldout, int64_t n,
 // ------------------------------------------------------------------ split
 size_t split_scratch_bytes(int64_t n, int K);
 template <typename T>
-int split_pow2(sphx_graph *g, const T *coords, int ld, int ncoord, int K,
-               int32_t *part, void *scratch, void *pinned, hipStream_t s,
-               std::string *err);
+int split_mj(sphx_graph *g, const T *coords, int ld, int ncoord, int K,
+             int32_t *part, void *scratch, void *pinned, hipStream_t s,
+             std::string *err);
 
 // ---------------------------------------------------------------- quality
 size_t quality_scratch_bytes(int K);

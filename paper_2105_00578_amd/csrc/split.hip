@@ -1,18 +1,24 @@
-// Coordinate split of the spectral embedding into K = 2^L parts (Algorithm 2,
-// the multi-jagged split specialised to bisections, Sec. 4).
+// Coordinate split of the spectral embedding into K parts (Algorithm 2, the
+// multi-jagged split of Sec. 4).
 //
-// Level l bisects every current section along coordinate l mod ncoord.  The
+// One level per prime factor p of K, largest first; level l splits every
+// current section into p children along coordinate l mod ncoord.  The
 // members of a section are ordered by the composite key (value, vertex id),
 // value mapped to an order-preserving unsigned integer with -0 == +0, so every
-// key is unique.  The lower child receives the prefix whose weight W_lo
-// minimises |2 W_lo - W|, the shorter prefix on ties.
+// key is unique.  Cut j (1 <= j < p) of a section of weight W follows the
+// prefix whose weight C minimises |p C - j W|, the shorter prefix on ties
+// (for p = 2: |2 W_lo - W|); children are the members between consecutive
+// cuts and part ids are the mixed-radix digits, most significant first.
 //
-// The prefix end is found without sorting: for every section a radix select
-// over the bytes of the composite key (most significant first) finds the
-// first member e* whose inclusive prefix weight reaches W/2; e* itself goes
-// low iff that brings |2 W_lo - W| strictly down.  Integer vertex weights
-// make every histogram exact, so the result does not depend on the order of
-// the atomic additions.
+// A cut is found without sorting: for every (section, cut) target a radix
+// select over the bytes of the composite key (most significant first) finds
+// the first member e* whose inclusive prefix weight C reaches j W / p; e*
+// itself is included iff that brings |p C - j W| strictly down.  Integer
+// vertex weights make every histogram exact, so the result does not depend
+// on the order of the atomic additions.
+#include <algorithm>
+#include <vector>
+
 #include "kernels.h"
 
 namespace sphx {
@@ -73,95 +79,123 @@ __device__ __forceinline__ bool prefix_match(K ord, uint32_t id, K pord, uint32_
   return (id & mask) == pid;
 }
 
-constexpr int kLdsSections = 16;
+constexpr int kLdsTargets = 16;
 
+// Histogram of byte d over the members of every target's section whose first
+// d key bytes match the target's prefix.  Target t = s * (p - 1) + j - 1.
 template <typename K, bool kLds>
 __global__ __launch_bounds__(256) void k_hist(int64_t n, const K *__restrict__ keys,
                                               const int32_t *__restrict__ part,
-                                              const int32_t *__restrict__ vwgt, int d,
-                                              int nsec, const K *__restrict__ pord,
+                                              const int32_t *__restrict__ vwgt, int d, int p,
+                                              int ntgt, const K *__restrict__ pord,
                                               const uint32_t *__restrict__ pid,
                                               unsigned long long *hist) {
-  __shared__ unsigned long long h[kLds ? kLdsSections * 256 : 1];
+  __shared__ unsigned long long h[kLds ? kLdsTargets * 256 : 1];
   if constexpr (kLds) {
-    for (int e = threadIdx.x; e < nsec * 256; e += blockDim.x) h[e] = 0;
+    for (int e = threadIdx.x; e < ntgt * 256; e += blockDim.x) h[e] = 0;
     __syncthreads();
   }
+  const int pm = p - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    int s = part[i];
-    K o = keys[i];
-    uint32_t id = (uint32_t)i;
-    if (!prefix_match(o, id, pord[s], pid[s], d)) continue;
-    unsigned long long wt = vwgt ? (unsigned long long)vwgt[i] : 1ull;
-    int b = digit(o, id, d);
-    if constexpr (kLds) atomicAdd(&h[s * 256 + b], wt);
-    else atomicAdd(&hist[(int64_t)s * 256 + b], wt);
+    const int s = part[i];
+    const K o = keys[i];
+    const uint32_t id = (uint32_t)i;
+    const unsigned long long wt = vwgt ? (unsigned long long)vwgt[i] : 1ull;
+    const int b = digit(o, id, d);
+    for (int j = 0; j < pm; ++j) {
+      const int t = s * pm + j;
+      if (!prefix_match(o, id, pord[t], pid[t], d)) continue;
+      if constexpr (kLds) atomicAdd(&h[t * 256 + b], wt);
+      else atomicAdd(&hist[(int64_t)t * 256 + b], wt);
+    }
   }
   if constexpr (kLds) {
     __syncthreads();
-    for (int e = threadIdx.x; e < nsec * 256; e += blockDim.x)
+    for (int e = threadIdx.x; e < ntgt * 256; e += blockDim.x)
       if (h[e]) atomicAdd(&hist[e], h[e]);
   }
 }
 
-// One thread per section: choose byte d, clear the histogram row.
+// One thread per target: choose byte d (the first bucket where p * C reaches
+// j * W), clear the histogram row.
 template <typename K>
-__global__ void k_select(int nsec, int d, int nd, unsigned long long *hist, K *pord,
+__global__ void k_select(int ntgt, int p, int d, int nd, unsigned long long *hist, K *pord,
                          uint32_t *pid, long long *base, const long long *W,
                          long long *wstar) {
   constexpr int OB = sizeof(K);
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsec) return;
-  long long Ws = W[s];
-  long long cum = base[s];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntgt) return;
+  const int s = t / (p - 1);
+  const long long jW = (long long)(t % (p - 1) + 1) * W[s];
+  long long cum = base[t];
   int chosen = -1;
   long long hb = 0;
   for (int b = 0; b < 256; ++b) {
-    long long v = (long long)hist[(int64_t)s * 256 + b];
-    hist[(int64_t)s * 256 + b] = 0;
+    long long v = (long long)hist[(int64_t)t * 256 + b];
+    hist[(int64_t)t * 256 + b] = 0;
     if (chosen < 0) {
-      if (v > 0 && 2 * (cum + v) >= Ws) { chosen = b; hb = v; }
+      if (v > 0 && (long long)p * (cum + v) >= jW) { chosen = b; hb = v; }
       else cum += v;
     }
   }
   if (chosen < 0) return;   // empty section
-  base[s] = cum;
-  if (d < OB) pord[s] |= (K)chosen << (8 * (OB - 1 - d));
-  else pid[s] |= (uint32_t)chosen << (8 * (3 - (d - OB)));
-  if (d == nd - 1) wstar[s] = hb;
+  base[t] = cum;
+  if (d < OB) pord[t] |= (K)chosen << (8 * (OB - 1 - d));
+  else pid[t] |= (uint32_t)chosen << (8 * (3 - (d - OB)));
+  if (d == nd - 1) wstar[t] = hb;
 }
 
-__global__ void k_finish_level(int nsec, const long long *base, const long long *W,
-                               const long long *wstar, int *incl, long long *Wnext) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsec) return;
-  long long Ws = W[s], b = base[s], ws = wstar[s];
+// Per target: include e* or not; lo[t] = weight of the prefix before the cut.
+__global__ void k_finish_targets(int ntgt, int p, const long long *base, const long long *W,
+                                 const long long *wstar, int *incl, long long *lo) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntgt) return;
+  const int s = t / (p - 1);
+  const long long Ws = W[s], b = base[t], ws = wstar[t];
+  const long long jW = (long long)(t % (p - 1) + 1) * Ws;
   int inc = 0;
-  if (Ws > 0) inc = (2 * (b + ws) - Ws) < (Ws - 2 * b) ? 1 : 0;
-  long long lo = b + (inc ? ws : 0);
-  if (Ws == 0) lo = 0;
-  incl[s] = inc;
-  Wnext[2 * s] = lo;
-  Wnext[2 * s + 1] = Ws - lo;
+  if (Ws > 0) inc = ((long long)p * (b + ws) - jW) < (jW - (long long)p * b) ? 1 : 0;
+  incl[t] = inc;
+  lo[t] = Ws > 0 ? b + (inc ? ws : 0) : 0;
 }
 
+// Per section: the weights of its p children.
+__global__ void k_finish_sections(int nsec, int p, const long long *lo, const long long *W,
+                                  long long *Wnext) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsec) return;
+  long long prev = 0;
+  for (int c = 0; c < p; ++c) {
+    const long long cur = c < p - 1 ? lo[s * (p - 1) + c] : W[s];
+    Wnext[(int64_t)s * p + c] = cur - prev;
+    prev = cur;
+  }
+}
+
+// child = number of cuts of the member's section that it lies after
 template <typename K>
-__global__ void k_assign(int64_t n, const K *keys, int32_t *part, const K *pord,
+__global__ void k_assign(int64_t n, const K *keys, int32_t *part, int p, const K *pord,
                          const uint32_t *pid, const int *incl, const long long *W) {
+  const int pm = p - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    int s = part[i];
-    K o = keys[i];
-    uint32_t id = (uint32_t)i;
-    K po = pord[s];
-    uint32_t pi = pid[s];
-    bool low;
-    if (W[s] == 0) low = false;
-    else if (o != po) low = o < po;
-    else if (id != pi) low = id < pi;
-    else low = incl[s] != 0;
-    part[i] = 2 * s + (low ? 0 : 1);
+    const int s = part[i];
+    const K o = keys[i];
+    const uint32_t id = (uint32_t)i;
+    int child = 0;
+    if (W[s] != 0)
+      for (int j = 0; j < pm; ++j) {
+        const int t = s * pm + j;
+        const K po = pord[t];
+        const uint32_t pi = pid[t];
+        bool low;
+        if (o != po) low = o < po;
+        else if (id != pi) low = id < pi;
+        else low = incl[t] != 0;
+        child += low ? 0 : 1;
+      }
+    part[i] = s * p + child;
   }
 }
 
@@ -182,26 +216,39 @@ __global__ void k_wsum(int64_t n, const int32_t *vwgt, long long *out) {
 }  // namespace
 
 size_t split_scratch_bytes(int64_t n, int K) {
+  // targets of a level (nsec * (p - 1)), sections and children all fit in K
   int64_t ns = K < 1 ? 1 : K;
   size_t b = 0;
   b += align_up(sizeof(uint64_t) * n, 256);                 // keys
-  b += align_up(sizeof(unsigned long long) * ns * 256, 256); // hist (K/2 sections max)
+  b += align_up(sizeof(unsigned long long) * ns * 256, 256); // hist (one row per target)
   b += align_up(sizeof(uint64_t) * ns, 256);                // pord
   b += align_up(sizeof(uint32_t) * ns, 256);                // pid
-  b += align_up(sizeof(long long) * ns, 256) * 3;           // base, wstar, W
-  b += align_up(sizeof(long long) * 2 * ns, 256);           // Wnext
+  b += align_up(sizeof(long long) * ns, 256) * 4;           // base, wstar, W, lo
+  b += align_up(sizeof(long long) * ns, 256);               // Wnext
   b += align_up(sizeof(int) * ns, 256);                     // incl
   b += 1024;
   return b;
 }
 
+std::vector<int> section_counts(int K) {
+  std::vector<int> f;
+  int k = K;
+  for (int q = 2; (int64_t)q * q <= k; ++q)
+    while (k % q == 0) {
+      f.push_back(q);
+      k /= q;
+    }
+  if (k > 1) f.push_back(k);
+  std::sort(f.begin(), f.end(), [](int a, int b) { return a > b; });
+  return f;
+}
+
 template <typename T>
-int split_pow2(sphx_graph *g, const T *coords, int ld, int ncoord, int K, int32_t *part,
-               void *scratch, void *pinned, hipStream_t s, std::string *err) {
+int split_mj(sphx_graph *g, const T *coords, int ld, int ncoord, int K, int32_t *part,
+             void *scratch, void *pinned, hipStream_t s, std::string *err) {
   using KT = typename Ord<T>::K;
   const int64_t n = g->n;
-  int levels = 0;
-  while ((1 << levels) < K) ++levels;
+  const std::vector<int> counts = section_counts(K);
   Arena a;
   a.base = static_cast<char *>(scratch);
   a.cap = split_scratch_bytes(n, K);
@@ -212,7 +259,8 @@ int split_pow2(sphx_graph *g, const T *coords, int ld, int ncoord, int K, int32_
   long long *base = a.take<long long>(K);
   long long *wstar = a.take<long long>(K);
   long long *W = a.take<long long>(K);
-  long long *Wnext = a.take<long long>(2 * (size_t)K);
+  long long *lo = a.take<long long>(K);
+  long long *Wnext = a.take<long long>(K);
   int *incl = a.take<int>(K);
   int *flag = a.take<int>(4);
   hipMemsetAsync(part, 0, sizeof(int32_t) * n, s);
@@ -222,27 +270,32 @@ int split_pow2(sphx_graph *g, const T *coords, int ld, int ncoord, int K, int32_
   hipLaunchKernelGGL(k_wsum, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, n, g->vwgt, W);
   const int nd = (int)sizeof(KT) + 4;
   const unsigned gn = grid_for(n, 256, 4096);
-  for (int l = 0; l < levels; ++l) {
-    const int nsec = 1 << l;
-    const int c = l % ncoord;
+  int nsec = 1;
+  for (size_t l = 0; l < counts.size(); ++l) {
+    const int p = counts[l];
+    const int ntgt = nsec * (p - 1);
+    const int c = (int)(l % (size_t)ncoord);
+    const unsigned gt = grid_for(ntgt, 256, 1 << 16);
     hipLaunchKernelGGL((k_keys<T>), dim3(gn), dim3(256), 0, s, coords, ld, c, n, keys, flag);
-    hipLaunchKernelGGL((k_reset<KT>), dim3(grid_for(nsec, 256, 1 << 16)), dim3(256), 0, s,
-                       nsec, pord, pid, base);
+    hipLaunchKernelGGL((k_reset<KT>), dim3(gt), dim3(256), 0, s, ntgt, pord, pid, base);
     for (int d = 0; d < nd; ++d) {
-      if (nsec <= kLdsSections)
+      if (ntgt <= kLdsTargets)
         hipLaunchKernelGGL((k_hist<KT, true>), dim3(gn), dim3(256), 0, s, n, keys, part,
-                           g->vwgt, d, nsec, pord, pid, hist);
+                           g->vwgt, d, p, ntgt, pord, pid, hist);
       else
         hipLaunchKernelGGL((k_hist<KT, false>), dim3(gn), dim3(256), 0, s, n, keys, part,
-                           g->vwgt, d, nsec, pord, pid, hist);
-      hipLaunchKernelGGL((k_select<KT>), dim3(grid_for(nsec, 256, 1 << 16)), dim3(256), 0, s,
-                         nsec, d, nd, hist, pord, pid, base, W, wstar);
+                           g->vwgt, d, p, ntgt, pord, pid, hist);
+      hipLaunchKernelGGL((k_select<KT>), dim3(gt), dim3(256), 0, s, ntgt, p, d, nd, hist, pord,
+                         pid, base, W, wstar);
     }
-    hipLaunchKernelGGL(k_finish_level, dim3(grid_for(nsec, 256, 1 << 16)), dim3(256), 0, s,
-                       nsec, base, W, wstar, incl, Wnext);
-    hipLaunchKernelGGL((k_assign<KT>), dim3(gn), dim3(256), 0, s, n, keys, part, pord, pid,
+    hipLaunchKernelGGL(k_finish_targets, dim3(gt), dim3(256), 0, s, ntgt, p, base, W, wstar,
+                       incl, lo);
+    hipLaunchKernelGGL(k_finish_sections, dim3(grid_for(nsec, 256, 1 << 16)), dim3(256), 0, s,
+                       nsec, p, lo, W, Wnext);
+    hipLaunchKernelGGL((k_assign<KT>), dim3(gn), dim3(256), 0, s, n, keys, part, p, pord, pid,
                        incl, W);
-    hipMemcpyAsync(W, Wnext, sizeof(long long) * 2 * nsec, hipMemcpyDeviceToDevice, s);
+    nsec *= p;
+    hipMemcpyAsync(W, Wnext, sizeof(long long) * nsec, hipMemcpyDeviceToDevice, s);
   }
   if (hipGetLastError() != hipSuccess) {
     *err = "split kernel launch failed";
@@ -261,9 +314,9 @@ int split_pow2(sphx_graph *g, const T *coords, int ld, int ncoord, int K, int32_
   return SPHX_OK;
 }
 
-template int split_pow2<float>(sphx_graph *, const float *, int, int, int, int32_t *, void *,
-                               void *, hipStream_t, std::string *);
-template int split_pow2<double>(sphx_graph *, const double *, int, int, int, int32_t *, void *,
-                                void *, hipStream_t, std::string *);
+template int split_mj<float>(sphx_graph *, const float *, int, int, int, int32_t *, void *,
+                             void *, hipStream_t, std::string *);
+template int split_mj<double>(sphx_graph *, const double *, int, int, int, int32_t *, void *,
+                              void *, hipStream_t, std::string *);
 
 }  // namespace sphx

@@ -121,3 +121,57 @@ def test_partition_end_to_end_grid64(handle, prec):
     # valid embedding: axis-aligned coordinates give the quadrant cut (128),
     # the 45-degree rotation two staircase cuts (about 256)
     assert cut <= 2.1 * 128
+
+
+# ---- general K: multi-jagged with one level per prime factor of K
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("K", [3, 5, 6, 7, 12, 24, 30, 96, 2500])
+@pytest.mark.parametrize("ties", [False, True])
+def test_split_general_k_bit_exact(handle, dtype, K, ties):
+    g = _grid(50)                          # n = 2500
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    rng = np.random.default_rng(K + 7)
+    coords = rng.standard_normal((g.n, 4))
+    if ties:
+        coords = np.round(coords, 1)
+    coords = coords.astype(dtype)
+    part = sx.split(handle, G, torch.from_numpy(coords).to(dev()), K).cpu().numpy()
+    assert np.array_equal(part, split.split_mj(coords, K))
+
+
+@pytest.mark.parametrize("K", [3, 24, 45])
+def test_split_general_k_weighted(handle, K):
+    g = random_graph(3000, 0.001, 2)
+    rng = np.random.default_rng(K)
+    vw = rng.integers(1, 20, g.n).astype(np.int32)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w, vwgt=torch.from_numpy(vw).to(dev()))
+    V = rng.standard_normal((g.n, 5)).astype(np.float32)
+    Vd = torch.from_numpy(V).to(dev())
+    part = sx.split(handle, G, Vd[:, 1:], K, ld=5, ncoord=4).cpu().numpy()
+    ref = split.split_mj(V[:, 1:], K, vw)
+    assert np.array_equal(part, ref)
+    cut, cut2, imb, pw = sx.quality(handle, G, torch.from_numpy(ref).to(dev()), K)
+    assert np.array_equal(pw, quality.part_weights(ref, K, vw))
+
+
+@pytest.mark.parametrize("K", [24, 6])
+def test_partition_general_k_grid(handle, K):
+    """Algorithm 2 with K = 24 (the paper's K, d = 5) on a 3D 7-point 32^3 grid."""
+    n, (u, v) = graphgen.grid3d_7pt(32, 32, 32)
+    g = graphgen.csr_from_edges(n, u, v)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    opts = sx.options_default(True, sx.PRECOND_CHEBYSHEV, precision=sx.FP64, seed=3)
+    lam, V, part, cut, imb, st = sx.partition(handle, G, K, opts)
+    assert len(lam) == sx.num_eigenvectors(K)
+    Vh = V.cpu().numpy()
+    ref = split.split_mj(Vh[:, 1:], K)
+    assert np.array_equal(part.cpu().numpy(), ref)
+    c_ref, _ = quality.cutsize(g.rowptr, g.col, None, ref)
+    assert cut == c_ref
+    assert imb == quality.imbalance(ref, K)
+    sizes = np.bincount(ref, minlength=K)
+    assert sizes.min() >= n // K and sizes.max() <= -(-n // K)

@@ -121,6 +121,39 @@ def brick27(nx: int, ny: int, nz: int):
     return nx * ny * nz, grid_edges((nz, ny, nx), _half_offsets(3, full=True))
 
 
+def brick27_csr(nx: int, ny: int, nz: int, name: str = "") -> "Graph":
+    """CSR of the 27-point brick built row by row (no edge list or sort):
+    the same graph as csr_from_edges on brick27, for sizes where the edge
+    list would be large.  Rows are vertices z*ny*nx + y*nx + x."""
+    n = nx * ny * nz
+    offs = sorted(((dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+                   if (dz, dy, dx) != (0, 0, 0)),
+                  key=lambda o: o[0] * ny * nx + o[1] * nx + o[2])
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % nx
+    y = (idx // nx) % ny
+    z = idx // (nx * ny)
+    del idx
+    valid = np.empty((n, len(offs)), dtype=bool)
+    for q, (dz, dy, dx) in enumerate(offs):
+        valid[:, q] = ((x + dx >= 0) & (x + dx < nx) & (y + dy >= 0) & (y + dy < ny)
+                       & (z + dz >= 0) & (z + dz < nz))
+    counts = valid.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    delta = np.array([o[0] * ny * nx + o[1] * nx + o[2] for o in offs], dtype=np.int64)
+    col = np.empty(int(rowptr[-1]), dtype=np.int32)
+    rows = np.arange(n, dtype=np.int64)
+    # fill by rows in chunks: columns of a row are its valid offsets in
+    # increasing delta order, hence sorted
+    chunk = 1 << 20
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        cand = rows[lo:hi, None] + delta[None, :]
+        col[rowptr[lo]:rowptr[hi]] = cand[valid[lo:hi]].astype(np.int32)
+    return Graph(n=n, rowptr=rowptr, col=col, w=None, name=name or f"brick27_{nx}x{ny}x{nz}")
+
+
 # ----------------------------------------------------------------------------
 # R-MAT and long-range edges
 # ----------------------------------------------------------------------------
@@ -280,6 +313,9 @@ CONFIGS = {
     "brick96lr": "3D 27-point 96^3 + 1% long-range edges, weights U[0.5,1.5) fp32",
     "king512": "2D 9-point grid 512x512, weights U[0.5,1.5) fp64",
     "rmat18": "R-MAT scale 18, edge factor 16, LCC, weights U[0.5,1.5) fp64",
+    "brick100": "Galeri Brick3D 27-point 100^3, unit weights (the paper's synthetic mesh)",
+    "brick200": "Galeri Brick3D 27-point 200^3, unit weights",
+    "brick400": "Galeri Brick3D 27-point 400^3, unit weights",
 }
 
 
@@ -335,4 +371,7 @@ def config_graph(name: str, graph_seed: int = 1, weight_seed: int = 0,
         sc = 18 - int(np.log2(scale_down))
         return rmat_graph(sc, seed=graph_seed, weight_seed=weight_seed,
                           weight_dtype=np.float64)
+    if name in ("brick100", "brick200", "brick400"):
+        s = max(3, int(name[5:]) // scale_down)
+        return brick27_csr(s, s, s, name=f"brick27_{s}^3")
     raise KeyError(name)

@@ -6,19 +6,28 @@
 namespace sphx {
 
 // ------------------------------------------------------------------ setup
-// Row bins for the Laplacian product: rows with at most kShortDeg neighbours
-// are processed by a lane group each, rows up to kHubDeg by a wavefront
-// each, longer rows in kHubChunk-entry chunks by one wavefront per chunk.
-constexpr int kShortDeg = 32;
+// Row classes of the Laplacian product by neighbour count.  Class c < kNumBins
+// holds rows with at most bin_max_deg(c) neighbours (and more than the class
+// below), served by bin_group(c) lanes per row; rows beyond kHubDeg are hubs,
+// split into kHubChunk-entry chunks of one wavefront each.
 constexpr int kHubDeg = 16384;
 constexpr int kHubChunk = 4096;
+constexpr int kNumBins = 4;
+__host__ __device__ constexpr int bin_max_deg(int c) {
+  return c == 0 ? 12 : (c == 1 ? 48 : (c == 2 ? 192 : kHubDeg));
+}
+__host__ __device__ constexpr int bin_group(int c) {
+  return c == 0 ? 1 : (c == 1 ? 4 : (c == 2 ? 16 : 64));
+}
+// Graphs whose rows all have at most this many neighbours are not binned:
+// every row in natural order, `group` lanes per row.
+constexpr int kUnbinnedMaxDeg = 48;
 
 struct SpmmPlan {
-  bool binned = false;          // false: every row is short, natural order
-  const int32_t *short_rows = nullptr;
-  int64_t n_short = 0;
-  const int32_t *mid_rows = nullptr;
-  int64_t n_mid = 0;
+  bool binned = false;          // false: natural row order, `group` lanes per row
+  int group = 1;
+  const int32_t *rows[kNumBins] = {};    // row lists of the classes (binned)
+  int64_t nrows[kNumBins] = {};
   const int32_t *hub_rows = nullptr;     // hub rows
   int64_t n_hub = 0;
   const int64_t *chunk_k0 = nullptr;     // per chunk: first entry

@@ -189,19 +189,22 @@ __global__ __launch_bounds__(256) void k_wrange(int64_t nnz, const WT *w, double
   }
 }
 
-// Deterministic three-way row binning: class 0 short, 1 mid, 2 hub.
+// Deterministic row binning into kNumBins + 1 classes (the last = hubs).
 constexpr int kBinRows = 1024;   // rows per block
+constexpr int kNumCls = kNumBins + 1;
 
 template <typename IdxT>
 __device__ __forceinline__ int row_class(const IdxT *rp, int64_t i) {
-  int64_t d = rp[i + 1] - rp[i];
-  return d <= kShortDeg ? 0 : (d <= kHubDeg ? 1 : 2);
+  const int64_t d = rp[i + 1] - rp[i];
+  int c = 0;
+  while (c < kNumBins && d > bin_max_deg(c)) ++c;
+  return c;
 }
 
 template <typename IdxT>
 __global__ __launch_bounds__(256) void k_bin_count(int64_t n, const IdxT *rp, int *counts) {
-  __shared__ int c[3];
-  if (threadIdx.x < 3) c[threadIdx.x] = 0;
+  __shared__ int c[kNumCls];
+  if (threadIdx.x < kNumCls) c[threadIdx.x] = 0;
   __syncthreads();
   int64_t r0 = (int64_t)blockIdx.x * kBinRows;
   for (int t = threadIdx.x; t < kBinRows; t += blockDim.x) {
@@ -209,41 +212,47 @@ __global__ __launch_bounds__(256) void k_bin_count(int64_t n, const IdxT *rp, in
     if (i < n) atomicAdd(&c[row_class(rp, i)], 1);
   }
   __syncthreads();
-  if (threadIdx.x < 3) counts[blockIdx.x * 3 + threadIdx.x] = c[threadIdx.x];
+  if (threadIdx.x < kNumCls) counts[blockIdx.x * kNumCls + threadIdx.x] = c[threadIdx.x];
 }
 
+// Exclusive scan of the per-block counts into positions of one packed list
+// (class 0 rows first, then class 1, ...); totals[c] = rows of class c.
 __global__ void k_bin_scan(int nblocks, int *counts, int *totals) {
-  // single thread; nblocks <= n/1024
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    int acc[3] = {0, 0, 0};
+    int tot[kNumCls] = {};
     for (int b = 0; b < nblocks; ++b)
-      for (int c = 0; c < 3; ++c) {
-        int v = counts[b * 3 + c];
-        counts[b * 3 + c] = acc[c];
+      for (int c = 0; c < kNumCls; ++c) tot[c] += counts[b * kNumCls + c];
+    int base = 0;
+    int acc[kNumCls];
+    for (int c = 0; c < kNumCls; ++c) {
+      acc[c] = base;
+      base += tot[c];
+      totals[c] = tot[c];
+    }
+    for (int b = 0; b < nblocks; ++b)
+      for (int c = 0; c < kNumCls; ++c) {
+        int v = counts[b * kNumCls + c];
+        counts[b * kNumCls + c] = acc[c];
         acc[c] += v;
       }
-    totals[0] = acc[0];
-    totals[1] = acc[1];
-    totals[2] = acc[2];
   }
 }
 
 template <typename IdxT>
 __global__ __launch_bounds__(256) void k_bin_scatter(int64_t n, const IdxT *rp,
-                                                     const int *offsets, int32_t *l0,
-                                                     int32_t *l1, int32_t *l2) {
+                                                     const int *offsets, int32_t *packed) {
   // each thread owns kBinRows/256 consecutive rows; ranks via a block scan
-  __shared__ int cnt[3][256];
+  __shared__ int cnt[kNumCls][256];
   const int per = kBinRows / 256;
   int64_t r0 = (int64_t)blockIdx.x * kBinRows + (int64_t)threadIdx.x * per;
-  int local[3] = {0, 0, 0};
+  int local[kNumCls] = {};
   for (int t = 0; t < per; ++t) {
     int64_t i = r0 + t;
     if (i < n) local[row_class(rp, i)]++;
   }
-  for (int c = 0; c < 3; ++c) cnt[c][threadIdx.x] = local[c];
+  for (int c = 0; c < kNumCls; ++c) cnt[c][threadIdx.x] = local[c];
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < kNumCls) {
     int c = threadIdx.x, acc = 0;
     for (int t = 0; t < 256; ++t) {
       int v = cnt[c][t];
@@ -252,14 +261,13 @@ __global__ __launch_bounds__(256) void k_bin_scatter(int64_t n, const IdxT *rp,
     }
   }
   __syncthreads();
-  int pos[3];
-  for (int c = 0; c < 3; ++c) pos[c] = offsets[blockIdx.x * 3 + c] + cnt[c][threadIdx.x];
-  int32_t *lists[3] = {l0, l1, l2};
+  int pos[kNumCls];
+  for (int c = 0; c < kNumCls; ++c) pos[c] = offsets[blockIdx.x * kNumCls + c] + cnt[c][threadIdx.x];
   for (int t = 0; t < per; ++t) {
     int64_t i = r0 + t;
     if (i < n) {
       int c = row_class(rp, i);
-      lists[c][pos[c]++] = (int32_t)i;
+      packed[pos[c]++] = (int32_t)i;
     }
   }
 }
@@ -386,12 +394,11 @@ size_t plan_bytes(sphx_graph *g) {
   int64_t max_hub = g->nnz / kHubDeg + 1;
   int64_t max_chunks = g->nnz / kHubChunk + max_hub + 1;
   size_t b = 0;
-  b += align_up(sizeof(int32_t) * n, 256) * 2;          // short + mid lists
-  b += align_up(sizeof(int32_t) * (max_hub + 1), 256);  // hub list
+  b += align_up(sizeof(int32_t) * n, 256);              // packed class lists
   b += align_up(sizeof(int32_t) * (max_hub + 1), 256);  // hub chunk begin
   b += align_up(sizeof(int64_t) * max_chunks, 256) * 2; // chunk ranges
   b += align_up(sizeof(double) * max_chunks * kMaxNev, 256);
-  b += align_up(sizeof(int) * (nb * 3 + 3), 256);
+  b += align_up(sizeof(int) * (nb * kNumCls + kNumCls), 256);
   return b + 4096;
 }
 
@@ -402,40 +409,44 @@ int build_plan(sphx_graph *g, Arena &ws, SpmmPlan *plan, const DegreeStats &st,
   int64_t nb = ceil_div(n, kBinRows);
   int64_t max_hub = g->nnz / kHubDeg + 1;
   int64_t max_chunks = g->nnz / kHubChunk + max_hub + 1;
-  int32_t *l0 = ws.take<int32_t>(n);
-  int32_t *l1 = ws.take<int32_t>(n);
-  int32_t *l2 = ws.take<int32_t>(max_hub + 1);
+  int32_t *packed = ws.take<int32_t>(n);
   int32_t *hcb = ws.take<int32_t>(max_hub + 1);
   int64_t *k0 = ws.take<int64_t>(max_chunks);
   int64_t *k1 = ws.take<int64_t>(max_chunks);
   double *hp = ws.take<double>(max_chunks * kMaxNev);
-  int *counts = ws.take<int>(nb * 3 + 3);
-  if (st.max_deg <= kShortDeg) return SPHX_OK;   // natural order, one kernel
+  int *counts = ws.take<int>(nb * kNumCls + kNumCls);
+  if (st.max_deg <= kUnbinnedMaxDeg) {   // natural order, one group size
+    plan->group = st.max_deg <= bin_max_deg(0) ? bin_group(0) : bin_group(1);
+    return SPHX_OK;
+  }
   plan->binned = true;
-  int *totals = counts + nb * 3;
+  int *totals = counts + nb * kNumCls;
   if (g->rp64) {
     hipLaunchKernelGGL((k_bin_count<int64_t>), dim3(nb), dim3(256), 0, s, n,
                        (const int64_t *)g->rowptr, counts);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1), 0, s, (int)nb, counts, totals);
     hipLaunchKernelGGL((k_bin_scatter<int64_t>), dim3(nb), dim3(256), 0, s, n,
-                       (const int64_t *)g->rowptr, counts, l0, l1, l2);
+                       (const int64_t *)g->rowptr, counts, packed);
   } else {
     hipLaunchKernelGGL((k_bin_count<int32_t>), dim3(nb), dim3(256), 0, s, n,
                        (const int32_t *)g->rowptr, counts);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1), 0, s, (int)nb, counts, totals);
     hipLaunchKernelGGL((k_bin_scatter<int32_t>), dim3(nb), dim3(256), 0, s, n,
-                       (const int32_t *)g->rowptr, counts, l0, l1, l2);
+                       (const int32_t *)g->rowptr, counts, packed);
   }
   SPHX_HIP(g->h, hipGetLastError());
   int *th = static_cast<int *>(pinned);
-  SPHX_HIP(g->h, hipMemcpyAsync(th, totals, sizeof(int) * 3, hipMemcpyDeviceToHost, s));
+  SPHX_HIP(g->h, hipMemcpyAsync(th, totals, sizeof(int) * kNumCls, hipMemcpyDeviceToHost, s));
   SPHX_HIP(g->h, hipStreamSynchronize(s));
-  plan->short_rows = l0;
-  plan->n_short = th[0];
-  plan->mid_rows = l1;
-  plan->n_mid = th[1];
+  int64_t base = 0;
+  for (int c = 0; c < kNumBins; ++c) {
+    plan->rows[c] = packed + base;
+    plan->nrows[c] = th[c];
+    base += th[c];
+  }
+  const int32_t *l2 = packed + base;
   plan->hub_rows = l2;
-  plan->n_hub = th[2];
+  plan->n_hub = th[kNumBins];
   plan->hub_chunk_begin = hcb;
   plan->chunk_k0 = k0;
   plan->chunk_k1 = k1;

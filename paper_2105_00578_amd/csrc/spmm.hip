@@ -5,9 +5,11 @@
 // column-lane mapping: a group of G lanes serves one row, lane c owning
 // column cm.col[c], so the G values of a gathered neighbour row are read by G
 // adjacent lanes from one contiguous segment.  Rows are split by degree:
-//   short rows (deg <= kShortDeg): one lane group per row, 64/G rows per wave;
-//   mid rows: one wavefront per row, its 64/G groups striding over the
-//     neighbours, combined with cross-lane shuffles in a fixed order;
+//   rows of the lower degree classes: one lane group per row, 64/G rows per
+//     wave;
+//   rows of the highest class below the hubs: one wavefront per row, its
+//     64/G groups striding over the neighbours, combined with cross-lane
+//     shuffles in a fixed order;
 //   hub rows (deg > kHubDeg): kHubChunk-entry chunks, one wavefront each,
 //     partial sums combined per row in a second kernel (fixed order).
 // All sums are in a fixed order, so results are bitwise reproducible.
@@ -289,15 +291,19 @@ void run_all(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan,
     hipLaunchKernelGGL((k_spmm_group<T, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
                        A, (const int32_t *)nullptr, n, X, ldx, cm, epi, partials, slot(gb));
   } else {
-    if (plan.n_short > 0) {
-      unsigned gb = grid_for(plan.n_short, 4 * gpw, kGroupBlocks);
+    // rows of the first kNumBins - 1 classes: one lane group per row; the
+    // last class: one wavefront per row
+    for (int c = 0; c < kNumBins - 1; ++c) {
+      if (plan.nrows[c] == 0) continue;
+      unsigned gb = grid_for(plan.nrows[c], 4 * gpw, kGroupBlocks);
       hipLaunchKernelGGL((k_spmm_group<T, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
-                         A, plan.short_rows, plan.n_short, X, ldx, cm, epi, partials, slot(gb));
+                         A, plan.rows[c], plan.nrows[c], X, ldx, cm, epi, partials, slot(gb));
     }
-    if (plan.n_mid > 0) {
-      unsigned gb = grid_for(plan.n_mid, 4, kWaveBlocks);
+    if (plan.nrows[kNumBins - 1] > 0) {
+      unsigned gb = grid_for(plan.nrows[kNumBins - 1], 4, kWaveBlocks);
       hipLaunchKernelGGL((k_spmm_wave<T, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
-                         A, plan.mid_rows, plan.n_mid, X, ldx, cm, epi, partials, slot(gb));
+                         A, plan.rows[kNumBins - 1], plan.nrows[kNumBins - 1], X, ldx, cm, epi,
+                         partials, slot(gb));
     }
     if (plan.n_hub > 0) {
       unsigned gb = grid_for(plan.n_chunks, 4, kWaveBlocks);

@@ -248,30 +248,49 @@ __device__ __forceinline__ void wave_sum(typename Vec<T, VB>::type (&acc)[NV]) {
     }
 }
 
-// Mid rows: one wavefront per row.
-template <typename T, int VB, int NV, typename IdxT, typename WT, typename Epi>
-__global__ __launch_bounds__(256) void k_vrow_wave(Csr<IdxT, WT> A,
-                                                   const int32_t *__restrict__ rows,
-                                                   int64_t nrows, const T *__restrict__ Xs,
-                                                   int ld, Epi epi, double *partials, int slot0,
-                                                   int m) {
+template <typename T, int VB, int NV, int G>
+__device__ __forceinline__ void group_sum(typename Vec<T, VB>::type (&acc)[NV]) {
+  constexpr int E = Vec<T, VB>::E;
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      T a = acc[v][e];
+#pragma unroll
+      for (int off = G / 2; off >= 1; off >>= 1) a += __shfl_xor(a, off);
+      acc[v][e] = a;
+    }
+}
+
+// G lanes per row (G = 4, 16 or 64): the lanes of a group take every G-th
+// neighbour of the row, so a group reads a contiguous run of the column
+// indices; the group's partial sums are combined by a butterfly in a fixed
+// order and the group's first lane runs the epilogue.  rows = null: natural
+// order over all n rows.
+template <typename T, int VB, int NV, int G, typename IdxT, typename WT, typename Epi>
+__global__ __launch_bounds__(256) void k_vgroup(Csr<IdxT, WT> A,
+                                                const int32_t *__restrict__ rows,
+                                                int64_t nrows, const T *__restrict__ Xs,
+                                                int ld, Epi epi, double *partials, int slot0,
+                                                int m) {
   using V = typename Vec<T, VB>::type;
   constexpr int LD = NV * Vec<T, VB>::E;
+  constexpr int GPB = 256 / G;   // groups per block
   const V *X = reinterpret_cast<const V *>(Xs);
   const int ldv = ld / Vec<T, VB>::E;
-  const int lane = threadIdx.x & 63;
+  const int gl = threadIdx.x & (G - 1);
   double n1[LD], n2[LD];
 #pragma unroll
   for (int c = 0; c < LD; ++c) { n1[c] = 0.0; n2[c] = 0.0; }
-  for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < nrows;
-       r += (int64_t)gridDim.x * 4) {
-    const int64_t i = rows[r];
+  for (int64_t r = (int64_t)blockIdx.x * GPB + threadIdx.x / G; r < nrows;
+       r += (int64_t)gridDim.x * GPB) {
+    const int64_t i = rows ? rows[r] : r;
     V xi[NV], acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
-    vrow_acc<T, VB, NV>(A, (int64_t)A.rp[i] + lane, (int64_t)A.rp[i + 1], 64, X, ldv, xi, acc);
-    wave_sum<T, VB, NV>(acc);
-    if (lane == 0) epi.row(i, xi, acc, n1, n2);
+    vrow_acc<T, VB, NV>(A, (int64_t)A.rp[i] + gl, (int64_t)A.rp[i + 1], G, X, ldv, xi, acc);
+    group_sum<T, VB, NV, G>(acc);
+    if (gl == 0) epi.row(i, xi, acc, n1, n2);
   }
   if constexpr (Epi::kNorms) block_norms<LD>(n1, n2, m, partials, slot0 + (int)blockIdx.x);
 }
@@ -345,30 +364,51 @@ __global__ __launch_bounds__(256) void k_vhub_combine(const int32_t *__restrict_
 
 // ----------------------------------------------------------------- dispatch
 constexpr int kMaxShortBlocks = 8192;
+constexpr int kGroupBlocks = 8192;
+constexpr int kBinnedShortBlocks = 4096;
+constexpr int kBinnedGroupBlocks = 1536;
 constexpr int kWaveBlocks = 1024;
 constexpr int kHubBlocks = 16;
+static_assert(kMaxShortBlocks <= kMaxNormBlocks && kGroupBlocks <= kMaxNormBlocks &&
+                  kBinnedShortBlocks + (kNumBins - 1) * kBinnedGroupBlocks + kHubBlocks <=
+                      kMaxNormBlocks,
+              "norm partial slots");
 
 template <typename T, int VB, int NV, typename IdxT, typename WT, typename Epi>
 void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X, int ld,
              const Epi &epi, double *partials, int *nparts, int m, hipStream_t s) {
+  // Every launch writes one norm-partial slot per block: the grids below
+  // stay within kMaxNormBlocks in total (grid-stride loops cover the rest).
   int used = 0;
-  auto short_rows = [&](const int32_t *rows, int64_t nr) {
+  auto short_rows = [&](const int32_t *rows, int64_t nr, int64_t maxb) {
     int64_t nb = ceil_div(nr, 256);
-    int rpt = (int)ceil_div(nb, kMaxShortBlocks);
+    int rpt = (int)ceil_div(nb, maxb);
     nb = ceil_div(nr, 256 * (int64_t)rpt);
-    hipLaunchKernelGGL((k_vrow<T, VB, NV, IdxT, WT, Epi>), dim3((unsigned)nb), dim3(256), 0, s, A,
-                       rows, nr, X, ld, rpt, epi, partials, used, m);
+    hipLaunchKernelGGL((k_vrow<T, VB, NV, IdxT, WT, Epi>), dim3((unsigned)nb), dim3(256), 0, s,
+                       A, rows, nr, X, ld, rpt, epi, partials, used, m);
     used += (int)nb;
   };
+  auto grouped = [&](int G, const int32_t *rows, int64_t nr, int64_t maxb) {
+    unsigned gb = grid_for(nr, 256 / G, maxb);
+    if (G == 4)
+      hipLaunchKernelGGL((k_vgroup<T, VB, NV, 4, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s, A,
+                         rows, nr, X, ld, epi, partials, used, m);
+    else if (G == 16)
+      hipLaunchKernelGGL((k_vgroup<T, VB, NV, 16, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
+                         A, rows, nr, X, ld, epi, partials, used, m);
+    else
+      hipLaunchKernelGGL((k_vgroup<T, VB, NV, 64, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
+                         A, rows, nr, X, ld, epi, partials, used, m);
+    used += (int)gb;
+  };
   if (!plan.binned) {
-    short_rows(nullptr, n);
+    if (plan.group == 1) short_rows(nullptr, n, kMaxShortBlocks);
+    else grouped(plan.group, nullptr, n, kGroupBlocks);
   } else {
-    if (plan.n_short > 0) short_rows(plan.short_rows, plan.n_short);
-    if (plan.n_mid > 0) {
-      unsigned gb = grid_for(plan.n_mid, 4, kWaveBlocks);
-      hipLaunchKernelGGL((k_vrow_wave<T, VB, NV, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s, A,
-                         plan.mid_rows, plan.n_mid, X, ld, epi, partials, used, m);
-      used += (int)gb;
+    for (int c = 0; c < kNumBins; ++c) {
+      if (plan.nrows[c] == 0) continue;
+      if (bin_group(c) == 1) short_rows(plan.rows[c], plan.nrows[c], kBinnedShortBlocks);
+      else grouped(bin_group(c), plan.rows[c], plan.nrows[c], kBinnedGroupBlocks);
     }
     if (plan.n_hub > 0) {
       unsigned gb = grid_for(plan.n_chunks, 4, kWaveBlocks);

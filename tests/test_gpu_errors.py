@@ -52,7 +52,8 @@ def test_argument_codes(handle):
     rp, col, w = upload(g)
     G = sx.Graph(handle, rp, col, w)
     opts = sx.Options()
-    assert _code(lambda: sx.partition(handle, G, 3, opts)) == -1      # K not a power of 2
+    assert _code(lambda: sx.partition(handle, G, 1, opts)) == -1      # K < 2
+    assert _code(lambda: sx.partition(handle, G, G.n + 1, opts)) == -1   # K > n
     assert _code(lambda: sx.partition(handle, G, 1, opts)) == -1
     assert _code(lambda: sx.eigensolve(handle, G, 50, opts)) == -1   # nev >= n
     bad = sx.Options(tol=-1.0)

@@ -67,3 +67,17 @@ def test_weighted_king_graph():
     assert g.n == 256 and g.w.dtype == np.float64
     assert g.n_edges == 2 * 15 * 16 + 2 * 15 * 15
     _check_csr(g)
+
+
+def test_brick27_csr_equals_edge_list_build():
+    n, (u, v) = graphgen.brick27(6, 5, 4)
+    a = graphgen.csr_from_edges(n, u, v)
+    b = graphgen.brick27_csr(6, 5, 4)
+    assert np.array_equal(a.rowptr, b.rowptr) and np.array_equal(a.col, b.col)
+
+
+def test_brick100_matches_the_paper_edge_count():
+    # the paper's Brick3D 100^3 row counts nnz(A + A^T + I) = 26,463,592
+    g = graphgen.config_graph("brick100", scale_down=1)
+    assert g.n == 1_000_000
+    assert int(g.rowptr[-1]) + g.n == 26_463_592

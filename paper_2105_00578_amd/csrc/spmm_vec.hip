@@ -53,52 +53,64 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
   return x * q + (x < r ? x : r) + pos;
 }
 
+// acc = sum over entries k0, k0 + step, ... < k1 of w_k (x_i - x_col[k]).
+// U independent partial sums (U gathers in flight per lane), combined in a
+// fixed order.
 template <typename T, int VB, int NV, typename IdxT, typename WT>
 __device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t k0, int64_t k1,
                                          int step, const typename Vec<T, VB>::type *__restrict__ X,
                                          int ldv, const typename Vec<T, VB>::type (&xi)[NV],
                                          typename Vec<T, VB>::type (&acc)[NV]) {
   using V = typename Vec<T, VB>::type;
-  V a0[NV], a1[NV];
+  constexpr int U = NV <= 2 ? 4 : 2;
+  V a[U][NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) { a0[v] = V(0); a1[v] = V(0); }
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a[u][v] = V(0);
   int64_t k = k0;
-  for (; k + step < k1; k += 2 * step) {
-    const int64_t j0 = A.col[k], j1 = A.col[k + step];
-    V x0[NV], x1[NV];
+  for (; k + (U - 1) * step < k1; k += U * step) {
+    int64_t j[U];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      x0[v] = X[j0 * ldv + v];
-      x1[v] = X[j1 * ldv + v];
-    }
-    if constexpr (std::is_same_v<WT, Unit>) {
+    for (int u = 0; u < U; ++u) j[u] = A.col[k + u * step];
+    V x[U][NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        a0[v] += xi[v] - x0[v];
-        a1[v] += xi[v] - x1[v];
-      }
-    } else {
-      const T w0 = T(A.w[k]), w1 = T(A.w[k + step]);
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        a0[v] += w0 * (xi[v] - x0[v]);
-        a1[v] += w1 * (xi[v] - x1[v]);
+      for (int v = 0; v < NV; ++v) x[u][v] = X[j[u] * ldv + v];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if constexpr (std::is_same_v<WT, Unit>) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a[u][v] += xi[v] - x[u][v];
+      } else {
+        const T wk = T(A.w[k + u * step]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a[u][v] += wk * (xi[v] - x[u][v]);
       }
     }
   }
-  if (k < k1) {
-    const int64_t j0 = A.col[k];
-    if constexpr (std::is_same_v<WT, Unit>) {
+  // tail: fewer than U entries left, into the partial sums in order
 #pragma unroll
-      for (int v = 0; v < NV; ++v) a0[v] += xi[v] - X[j0 * ldv + v];
-    } else {
-      const T w0 = T(A.w[k]);
+  for (int u = 0; u < U - 1; ++u) {
+    if (k < k1) {
+      const int64_t j0 = A.col[k];
+      if constexpr (std::is_same_v<WT, Unit>) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) a0[v] += w0 * (xi[v] - X[j0 * ldv + v]);
+        for (int v = 0; v < NV; ++v) a[u][v] += xi[v] - X[j0 * ldv + v];
+      } else {
+        const T w0 = T(A.w[k]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a[u][v] += w0 * (xi[v] - X[j0 * ldv + v]);
+      }
+      k += step;
     }
   }
 #pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = a0[v] + a1[v];
+  for (int v = 0; v < NV; ++v) {
+    if constexpr (U == 4) acc[v] = (a[0][v] + a[1][v]) + (a[2][v] + a[3][v]);
+    else acc[v] = a[0][v] + a[1][v];
+  }
 }
 
 // ------------------------------------------------------------- epilogues

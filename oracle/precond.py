@@ -76,3 +76,94 @@ def gershgorin_bound(d, problem):
     if problem in (laplacian.GENERALIZED, laplacian.NORMALIZED):
         return 2.0
     return 2.0 * float(np.max(d)) if len(d) else 0.0
+
+
+# ---- GMRES polynomial (Sec. 5.2: the paper's polynomial preconditioner)
+#
+# The polynomial is the GMRES residual polynomial pi of degree k + 1 of a
+# (k+1)-step Krylov process from a start vector b, with p(x) = (1 - pi(x)) / x
+# of degree k (the preconditioner M = p(A)).  Its roots are the harmonic Ritz
+# values of that Krylov space; for the self-adjoint operators here (L_C, or
+# D^-1 L_C in the D-inner product, or L_N) the process is Lanczos in the
+# B-inner product and the harmonic Ritz values are the eigenvalues of the
+# symmetric-definite pencil (H^T H, H_k) with H the (k+2) x (k+1) projection.
+# The roots are applied in modified Leja order (first the largest, then each
+# maximising the product of distances to the ones before), through
+#   p(A) v = sum_i pi_{i-1}(A) v / theta_i,  pi_i = pi_{i-1} (I - A / theta_i).
+# Reading taken (the paper gives no start vector): b is made B-orthogonal to
+# the trivial eigenvector first, so the polynomial addresses the non-trivial
+# spectrum.
+
+def _ops(rowptr, col, w, problem):
+    """(A, B diagonal, trivial vector) of the problem's preconditioned operator."""
+    d = laplacian.degrees(rowptr, col, w)
+    n = d.size
+    if problem == laplacian.GENERALIZED:
+        A = lambda Z: laplacian.apply(rowptr, col, w, Z) / (d if Z.ndim == 1 else d[:, None])
+        return A, d, np.ones(n)
+    if problem == laplacian.NORMALIZED:
+        A = lambda Z: laplacian.apply_normalized(rowptr, col, w, Z)
+        return A, np.ones(n), np.sqrt(d)
+    A = lambda Z: laplacian.apply(rowptr, col, w, Z)
+    return A, np.ones(n), np.ones(n)
+
+
+def gmres_poly_roots(rowptr, col, w, problem, b, degree):
+    """The degree + 1 roots (harmonic Ritz values, modified Leja order) of the
+    GMRES residual polynomial from start vector b."""
+    import scipy.linalg
+    A, bd, z = _ops(rowptr, col, w, problem)
+    k1 = degree + 1
+    b = np.asarray(b, dtype=np.float64).copy()
+    b -= z * ((z * bd) @ b) / ((z * bd) @ z)             # B-orthogonal to the trivial vector
+    V = np.zeros((b.size, k1 + 1))
+    H = np.zeros((k1 + 1, k1))
+    V[:, 0] = b / np.sqrt(b @ (bd * b))
+    for j in range(k1):
+        wv = A(V[:, j])
+        for _ in range(2):                               # Gram-Schmidt, twice
+            h = V[:, :j + 1].T @ (bd * wv)
+            wv = wv - V[:, :j + 1] @ h
+            H[:j + 1, j] += h
+        H[j + 1, j] = np.sqrt(wv @ (bd * wv))
+        if H[j + 1, j] <= 1e-12 * np.abs(H[:j + 1, j]).max():
+            # invariant Krylov space: its j + 1 Ritz values are exact roots
+            k1 = j + 1
+            H = H[:k1 + 1, :k1]
+            H[k1, k1 - 1] = 0.0
+            break
+        V[:, j + 1] = wv / H[j + 1, j]
+    Hk = 0.5 * (H[:k1, :k1] + H[:k1, :k1].T)
+    theta = scipy.linalg.eigh(H.T @ H, Hk, eigvals_only=True)
+    return leja_order(theta)
+
+
+def leja_order(theta):
+    """Modified Leja ordering: the largest |theta| first, then each next one
+    maximises the sum of log distances to those already chosen (lowest index
+    on ties)."""
+    theta = np.asarray(theta, dtype=np.float64)
+    left = list(range(theta.size))
+    first = max(left, key=lambda i: (abs(theta[i]), -i))
+    out = [first]
+    left.remove(first)
+    while left:
+        score = [sum(np.log(abs(theta[i] - theta[j])) for j in out) for i in left]
+        best = left[int(np.argmax(score))]
+        out.append(best)
+        left.remove(best)
+    return theta[out]
+
+
+def gmres_poly_apply(rowptr, col, w, problem, R, roots):
+    """H = p(A) R' with p from the roots: R' = D^-1 R for the generalized
+    problem (the preconditioner p(D^-1 L) D^-1, as for Chebyshev), R otherwise."""
+    A, bd, z = _ops(rowptr, col, w, problem)
+    R = np.asarray(R, dtype=np.float64)
+    prod = R / bd[:, None] if problem == laplacian.GENERALIZED else R.copy()
+    Y = np.zeros_like(prod)
+    for i, t in enumerate(roots):
+        Y = Y + prod / t
+        if i < len(roots) - 1:
+            prod = prod - A(prod) / t
+    return Y

@@ -63,7 +63,7 @@ def _random_weighted(n, p, seed):
 
 
 @pytest.mark.parametrize("problem", [lap.COMBINATORIAL, lap.GENERALIZED, lap.NORMALIZED])
-@pytest.mark.parametrize("pc", ["none", "jacobi", "cheb"])
+@pytest.mark.parametrize("pc", ["none", "jacobi", "cheb", "gmres"])
 def test_lobpcg_matches_dense_definition(problem, pc):
     g = _random_weighted(120, 0.04, 11)
     L, d = lap.dense(g.rowptr, g.col, g.w)
@@ -81,6 +81,10 @@ def test_lobpcg_matches_dense_definition(problem, pc):
            "jacobi": lambda R: precond.jacobi(R, diag),
            "cheb": lambda R: precond.chebyshev(g.rowptr, g.col, g.w, R, 8, hi / 30, hi, dinv,
                                                problem=problem)}
+    if pc == "gmres":
+        b = graphgen.normal_block(g.n, 1, 5)[:, 0]
+        roots = precond.gmres_poly_roots(g.rowptr, g.col, g.w, problem, b, 8)
+        pcs["gmres"] = lambda R: precond.gmres_poly_apply(g.rowptr, g.col, g.w, problem, R, roots)
     X0 = graphgen.normal_block(g.n, nev, 2)
     theta, X, it, rho = eigen.lobpcg(g.rowptr, g.col, g.w, problem, X0, pcs[pc], 1e-9)
     assert rho.max() <= 1e-8

@@ -248,3 +248,85 @@ def test_split_mj_relabelling_invariance():
     a = split.split_mj(C, 24)
     b = split.split_mj(C[perm], 24)
     assert np.array_equal(a[perm], b)
+
+
+# ---- GMRES polynomial (Sec. 5.2)
+
+def _kn_graph(n=9):
+    iu, ju = np.triu_indices(n, 1)
+    return graphgen.csr_from_edges(n, iu, ju)
+
+
+def test_gmres_poly_exact_inverse_on_few_eigenvalues():
+    # 6x5 torus: few distinct eigenvalues; with degree >= their count - 1 the
+    # GMRES residual polynomial vanishes on the spectrum and p(L) = L^+ on 1^perp
+    n, u, v = cf.torus_edges(6, 5)
+    g = graphgen.csr_from_edges(n, u, v)
+    L, d = lap.dense(g.rowptr, g.col, g.w)
+    lam = np.unique(np.round(np.linalg.eigvalsh(L), 9))
+    deg = len(lam) - 2                       # roots = degree + 1 = distinct non-zero eigenvalues
+    b = np.random.default_rng(1).standard_normal(n)
+    roots = precond.gmres_poly_roots(g.rowptr, g.col, None, lap.COMBINATORIAL, b, deg)
+    assert np.allclose(np.sort(roots), lam[1:], rtol=1e-8)
+    r = np.random.default_rng(2).standard_normal((n, 2))
+    r -= r.mean(axis=0)
+    H = precond.gmres_poly_apply(g.rowptr, g.col, None, lap.COMBINATORIAL, r, roots)
+    assert np.allclose(L @ H, r, atol=1e-8)
+
+
+def test_gmres_poly_minimises_residual_over_krylov():
+    # pi(A) b has the least norm among residual polynomials of degree k + 1:
+    # compare with a least-squares fit over the Krylov basis
+    g = _random_weighted_graph()
+    L, d = lap.dense(g.rowptr, g.col, g.w)
+    b = np.random.default_rng(3).standard_normal(g.n)
+    b -= b.mean()
+    k = 6
+    roots = precond.gmres_poly_roots(g.rowptr, g.col, g.w, lap.COMBINATORIAL, b, k)
+    pb = b.copy()
+    for t in roots:
+        pb = pb - (L @ pb) / t
+    Kr = np.stack([np.linalg.matrix_power(L, j) @ b for j in range(1, k + 2)], axis=1)
+    c, *_ = np.linalg.lstsq(Kr, b, rcond=None)
+    best = np.linalg.norm(b - Kr @ c)
+    assert np.linalg.norm(pb) == pytest.approx(best, rel=1e-6)
+    # on an eigenvector v (eigenvalue mu) the apply gives p(mu) v with
+    # 1 - mu p(mu) = pi(mu) = prod (1 - mu / theta_i)
+    lam_all, Vall = np.linalg.eigh(L)
+    for q in (1, 5, g.n - 1):
+        mu, v = lam_all[q], Vall[:, q]
+        Hv = precond.gmres_poly_apply(g.rowptr, g.col, g.w, lap.COMBINATORIAL, v[:, None], roots)
+        pi = np.prod(1 - mu / roots)
+        assert np.allclose(Hv[:, 0], (1 - pi) / mu * v, atol=1e-9 * max(1, abs((1 - pi) / mu)))
+
+
+def _random_weighted_graph(n=40, p=0.15, seed=3):
+    rng = np.random.default_rng(seed)
+    iu, ju = np.triu_indices(n, 1)
+    keep = rng.random(iu.size) < p
+    u = np.concatenate([iu[keep], np.arange(n - 1)])
+    v = np.concatenate([ju[keep], np.arange(1, n)])
+    key = np.unique(np.minimum(u, v) * n + np.maximum(u, v))
+    u, v = key // n, key % n
+    return graphgen.csr_from_edges(n, u, v, graphgen.uniform_weights(u.size, seed, dtype=np.float64))
+
+
+def test_gmres_poly_generalized_equals_normalized_and_leja():
+    # D^-1 L (D-inner product) from b and L_N from D^1/2 b share the Krylov
+    # projection, hence the roots; p(D^-1 L) D^-1 r = D^-1/2 p(L_N) D^-1/2 r
+    g = _random_weighted_graph()
+    d = lap.degrees(g.rowptr, g.col, g.w)
+    b = np.random.default_rng(4).standard_normal(g.n)
+    rg = precond.gmres_poly_roots(g.rowptr, g.col, g.w, lap.GENERALIZED, b, 8)
+    rn = precond.gmres_poly_roots(g.rowptr, g.col, g.w, lap.NORMALIZED, np.sqrt(d) * b, 8)
+    assert np.allclose(rg, rn, rtol=1e-9)
+    assert rg[0] == np.max(np.abs(rg))
+    R = np.random.default_rng(5).standard_normal((g.n, 3))
+    Hg = precond.gmres_poly_apply(g.rowptr, g.col, g.w, lap.GENERALIZED, R, rg)
+    s = 1 / np.sqrt(d)
+    Hn = precond.gmres_poly_apply(g.rowptr, g.col, g.w, lap.NORMALIZED, s[:, None] * R, rg)
+    assert np.allclose(Hg, s[:, None] * Hn, rtol=1e-9, atol=1e-12)
+    # roots lie in the non-trivial spectrum of D^-1 L (within [lambda_1, 2])
+    L, _ = lap.dense(g.rowptr, g.col, g.w)
+    ev = np.sort(np.linalg.eigvals(L / d[:, None]).real)
+    assert rg.min() >= ev[1] * (1 - 1e-9) and rg.max() <= ev[-1] * (1 + 1e-9)

@@ -153,6 +153,15 @@ WORKLOADS = {
     "brick100-cheb": dict(graph="brick100", K=24, precond="cheb",
                           desc="Galeri Brick3D 27-point 100^3, combinatorial, K=24 (d=5), "
                                "LOBPCG + Chebyshev degree 25, tol 1e-3"),
+    "grid7_128-gmres": dict(graph="grid7_128", K=64, precond="gmres",
+                            desc="3D 7-point grid 128^3, combinatorial Laplacian, K=64 (d=7), "
+                                 "LOBPCG + GMRES polynomial degree 25, tol 1e-3"),
+    "brick100-gmres": dict(graph="brick100", K=24, precond="gmres",
+                           desc="Galeri Brick3D 27-point 100^3, combinatorial, K=24 (d=5), "
+                                "LOBPCG + GMRES polynomial degree 25, tol 1e-3"),
+    "rmat22-gmres": dict(graph="rmat22", K=16, precond="gmres",
+                         desc="R-MAT scale 22 (LCC), normalized Laplacian, K=16 (d=5), "
+                              "LOBPCG + GMRES polynomial degree 25, tol 1e-2, piecewise start"),
 }
 
 
@@ -175,7 +184,8 @@ def run(args):
     reg, _, _ = G.info()
     K = wl["K"]
     d = sx.num_eigenvectors(K)
-    pc = sx.PRECOND_CHEBYSHEV if wl["precond"] == "cheb" else sx.PRECOND_JACOBI
+    pc = {"cheb": sx.PRECOND_CHEBYSHEV, "gmres": sx.PRECOND_GMRES,
+          "jacobi": sx.PRECOND_JACOBI}[wl["precond"]]
     base = dict(cheb_degree=25, cheb_ratio=args.cheb_ratio, seed=12345)
     opts = {
         "mixed": sx.options_default(reg, pc, precision=sx.MIXED, **base),
@@ -218,7 +228,7 @@ def run(args):
         results[name] = r
     mx = results["mixed"]
     f64 = results.get("fp64", mx)
-    cheb = pc == sx.PRECOND_CHEBYSHEV
+    cheb = pc in (sx.PRECOND_CHEBYSHEV, sx.PRECOND_GMRES)
     value = mx["cheb_gbs"] if cheb else mx["spmm_gbs"]
     tr = measured_traffic() if headline else None
     line = {
@@ -247,7 +257,8 @@ def run(args):
             "unit": "GB/s",
             "frac": round(value / HBM_PEAK_GBS, 4),
             "traffic": None if tr is None else tr["bytes_per_launch"],
-            "kernel": ("Chebyshev-step Laplacian product (FP32)" if cheb else
+            "kernel": (("Chebyshev-step" if pc == sx.PRECOND_CHEBYSHEV else "GMRES-polynomial-step")
+                       + " Laplacian product (FP32)" if cheb else
                        "Laplacian products with the fused residual / Jacobi epilogue (FP32)"),
             "avg_launch_us": round(mx["cheb_avg_us"], 3) if cheb else None,
             "launches": mx["cheb_calls"] if cheb else mx["spmm_calls"],

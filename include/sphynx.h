@@ -65,9 +65,10 @@ enum { SPHX_UNIT = 0, SPHX_F32 = 1, SPHX_F64 = 2 };
  * y = D^1/2 x with unit 2-norm.  It needs every weighted degree > 0. */
 enum { SPHX_COMBINATORIAL = 0, SPHX_GENERALIZED = 1, SPHX_NORMALIZED = 2 };
 
-/* preconditioner (Sec. 5): none, Jacobi (Sec. 5.1), Chebyshev polynomial
- * (Sec. 5.2 names a degree-25 polynomial preconditioner) */
-enum { SPHX_PRECOND_NONE = 0, SPHX_PRECOND_JACOBI = 1, SPHX_PRECOND_CHEBYSHEV = 2 };
+/* preconditioner (Sec. 5): none, Jacobi (Sec. 5.1), Chebyshev polynomial,
+ * or the GMRES polynomial the paper uses (Sec. 5.2; degree 25 by default) */
+enum { SPHX_PRECOND_NONE = 0, SPHX_PRECOND_JACOBI = 1, SPHX_PRECOND_CHEBYSHEV = 2,
+       SPHX_PRECOND_GMRES = 3 };
 
 /* arithmetic: all FP64, or FP32 sparse products / preconditioner / vector
  * updates with FP64 Gram matrices, Rayleigh-Ritz and norms */
@@ -86,7 +87,8 @@ typedef struct sphx_graph sphx_graph;
 typedef struct sphx_options {
     int problem;          /* SPHX_COMBINATORIAL / _GENERALIZED / _NORMALIZED */
     int precond;          /* SPHX_PRECOND_*                                  */
-    int cheb_degree;      /* SpMMs per Chebyshev apply (default 25)          */
+    int cheb_degree;      /* degree of the polynomial preconditioner: SpMMs
+                             per apply (default 25; GMRES: 1..47)             */
     double cheb_ratio;    /* Chebyshev interval [hi/ratio, hi]; hi bounds the
                              spectrum: 2 max_i d_i (Gershgorin) for L_C, 2 for
                              D^-1 L_C and L_N                                */
@@ -150,8 +152,8 @@ int sphx_num_eigenvectors(int K);
 
 /* Defaults of Sec. 6.3.1 ("Sphynx Default Settings") for a preconditioner:
  * regular graphs use the combinatorial problem; irregular graphs the
- * normalized one with the polynomial (Chebyshev) preconditioner and the
- * generalized one otherwise; the tolerance is 1e-3 on regular graphs and 1e-2
+ * normalized one with a polynomial (Chebyshev or GMRES) preconditioner and
+ * the generalized one otherwise; the tolerance is 1e-3 on regular graphs and 1e-2
  * on irregular ones; initial vectors are random on regular graphs and
  * piecewise constant on irregular ones (Sec. 6.2.1). */
 void sphx_options_default(sphx_options *opt, int graph_is_regular, int precond);
@@ -261,6 +263,29 @@ int sphx_partition(sphx_handle *h, sphx_graph *g, int K, const sphx_options *opt
                    const void *X0, double *eigvals, void *eigvecs,
                    int32_t *part, double *cut, double *imbalance,
                    sphx_stats *stats);
+
+/* GMRES polynomial (Sec. 5.2).  The preconditioner is p(A) with p of degree
+ * k the polynomial of the GMRES residual polynomial
+ * pi(x) = prod_{i=1}^{k+1} (1 - x / theta_i) = 1 - x p(x) of a (k+1)-step
+ * Krylov process from a start vector b; A = L_C (combinatorial), D^-1 L_C
+ * applied to D^-1 r (generalized), L_N (normalized).  b is made orthogonal
+ * (in the problem's B-inner product) to the trivial eigenvector first.
+ *
+ * sphx_poly_roots: the roots theta_i (harmonic Ritz values of a Lanczos
+ * process with full reorthogonalisation in FP64), modified Leja order (the
+ * largest first, then each maximising the product of distances to those
+ * before).  b: device FP64[n] in the problem's variables (y for L_N).
+ * roots: host double[degree + 1]; *nroots = degree + 1, or fewer when the
+ * Krylov space becomes invariant.  1 <= degree <= 47.
+ * The solver (SPHX_PRECOND_GMRES) draws b from its seed. */
+int sphx_poly_roots(sphx_handle *h, sphx_graph *g, int problem, int degree,
+                    const double *b, double *roots, int *nroots);
+/* H = p(A) R (generalized: p(D^-1 L_C) D^-1 R) for the polynomial with the
+ * given nonzero roots (host, applied in the given order): nroots - 1
+ * Laplacian products, p(A) v = sum_i pi_{i-1}(A) v / theta_i.  R, H: device
+ * n x m row-major of dtype F32/F64, 1 <= m <= 16, not overlapping. */
+int sphx_poly_apply(sphx_handle *h, sphx_graph *g, int problem, int nroots,
+                    const double *roots, int m, int dtype, const void *R, void *H);
 
 /* ---------------------------------------------------------------- adjoint */
 

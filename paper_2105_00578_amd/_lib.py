@@ -12,7 +12,7 @@ library_path = os.path.join(PKG, "libsphynx.so")
 OK, NOT_CONVERGED = 0, 1
 UNIT, F32, F64 = 0, 1, 2
 COMBINATORIAL, GENERALIZED, NORMALIZED = 0, 1, 2
-PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHEBYSHEV = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHEBYSHEV, PRECOND_GMRES = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 INIT_RANDOM, INIT_PIECEWISE, INIT_USER = 0, 1, 2
 SKIP_VALIDATE = 1
@@ -69,6 +69,10 @@ def _load():
                                           C.POINTER(C.c_size_t)]),
         "sphx_set_workspace": (C.c_int, [vp, vp, C.c_size_t]),
         "sphx_laplacian_apply": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int, vp, vp]),
+        "sphx_poly_roots": (C.c_int, [vp, vp, C.c_int, C.c_int, vp, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int)]),
+        "sphx_poly_apply": (C.c_int, [vp, vp, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                      C.c_int, C.c_int, vp, vp]),
         "sphx_precond_apply": (C.c_int, [vp, vp, C.POINTER(_Options), C.c_int, C.c_int, vp,
                                          vp]),
         "sphx_eigensolve": (C.c_int, [vp, vp, C.c_int, C.POINTER(_Options), vp, dp, vp,
@@ -296,6 +300,30 @@ def laplacian_apply(h: Handle, g: Graph, X, out=None, problem: int = COMBINATORI
     h._check(lib.sphx_laplacian_apply(h.h, g.g, problem, m, _dtype_code(X),
                                       C.c_void_p(_ptr(X)), C.c_void_p(_ptr(Y))))
     return Y
+
+
+def poly_roots(h: Handle, g: Graph, problem: int, degree: int, b):
+    """Roots (Leja order) of the GMRES residual polynomial from start vector b
+    (float64 device vector of length n)."""
+    import numpy as np
+    b = b.to(_torch().float64).contiguous()
+    roots = (C.c_double * (degree + 1))()
+    nr = C.c_int()
+    h._check(lib.sphx_poly_roots(h.h, g.g, problem, degree, C.c_void_p(_ptr(b)), roots,
+                                 C.byref(nr)))
+    return np.array(roots[: nr.value])
+
+
+def poly_apply(h: Handle, g: Graph, problem: int, roots, R, out=None):
+    """H = p(A) R for the GMRES polynomial with the given roots."""
+    torch = _torch()
+    R = R.contiguous()
+    H = torch.empty_like(R) if out is None else out
+    m = 1 if R.dim() == 1 else R.shape[1]
+    rr = (C.c_double * len(roots))(*[float(x) for x in roots])
+    h._check(lib.sphx_poly_apply(h.h, g.g, problem, len(roots), rr, m, _dtype_code(R),
+                                 C.c_void_p(_ptr(R)), C.c_void_p(_ptr(H))))
+    return H
 
 
 def precond_apply(h: Handle, g: Graph, opts: Options, R, out=None):

@@ -53,6 +53,8 @@ struct SolveWs {
   double *deg_scratch;
   int *flags;
   void *split_scratch, *quality_scratch;
+  void *poly_scratch;   // Lanczos basis of the GMRES polynomial (or null)
+  double *poly_b;
   T *V;        // eigenvectors when the caller passes none (partition)
   int32_t *part;
   SpmmPlan plan;
@@ -61,7 +63,7 @@ struct SolveWs {
 
 template <typename T>
 void layout(Arena &a, SolveWs<T> &w, int64_t n, int m, int K, size_t plan_b,
-            bool want_split) {
+            bool want_split, int poly_degree) {
   w.d64 = a.take<double>(n);
   w.dinv = a.take<double>(n);
   w.sq = a.take<double>(n);
@@ -103,6 +105,13 @@ void layout(Arena &a, SolveWs<T> &w, int64_t n, int m, int K, size_t plan_b,
     w.V = nullptr;
     w.part = nullptr;
   }
+  if (poly_degree > 0) {
+    w.poly_scratch = a.take<char>(poly_scratch_bytes(n, poly_degree));
+    w.poly_b = a.take<double>(n);
+  } else {
+    w.poly_scratch = nullptr;
+    w.poly_b = nullptr;
+  }
   w.plan_off = a.off;
   a.off += plan_b;
 }
@@ -112,8 +121,10 @@ bool valid_options(const sphx_options *o) {
   if (o->problem != SPHX_COMBINATORIAL && o->problem != SPHX_GENERALIZED &&
       o->problem != SPHX_NORMALIZED)
     return false;
-  if (o->precond < SPHX_PRECOND_NONE || o->precond > SPHX_PRECOND_CHEBYSHEV) return false;
+  if (o->precond < SPHX_PRECOND_NONE || o->precond > SPHX_PRECOND_GMRES) return false;
   if (o->precond == SPHX_PRECOND_CHEBYSHEV && (o->cheb_degree < 1 || !(o->cheb_ratio > 1.0)))
+    return false;
+  if (o->precond == SPHX_PRECOND_GMRES && (o->cheb_degree < 1 || o->cheb_degree + 1 > kMaxW))
     return false;
   if (o->precision != SPHX_FP64 && o->precision != SPHX_MIXED) return false;
   if (!(o->tol > 0.0) || o->max_iter < 0) return false;
@@ -345,6 +356,64 @@ int cheb_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, int l
   return SPHX_OK;
 }
 
+// H[:, cm] = p(L) R[:, cm] for the GMRES polynomial with the given roots
+// (Leja order; nroots = degree + 1), on the compacted block of the active
+// columns (`spare` and B1, B2 are n x ld buffers; `spare` may be R itself,
+// which is read before it is overwritten).  Returns the buffer holding the
+// result in the padded layout.
+template <typename T>
+int poly_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, int ld,
+               const ColMap &cm, const T *R, T *B1, T *B2, T *spare, const double *roots,
+               int nroots, const double *dinv, hipStream_t s, T **result, int64_t *calls,
+               int64_t *pcalls) {
+  const int64_t n = g->n;
+  const int na = cm.count;
+  const int lda = compact_ld(na);
+  const int rd = dinv ? 1 : 0;
+  const double b3 = spmm_bytes(g, plan, na, sizeof(T), 3, rd);
+  const double b4 = spmm_bytes(g, plan, na, sizeof(T), 4, rd);
+  const int k = nroots - 1;             // Laplacian products
+  // P_1 = s R (compacted) -> B2; Y -> B1; P_2, P_3, ... alternate spare / B2
+  hipLaunchKernelGGL(k_compact_cols<T>, dim3(grid_for(n * lda, 256, 4096)), dim3(256), 0, s,
+                     R, ld, cm, lda, (const double *)nullptr, 1.0, B2, (T *)nullptr, n);
+  if (dinv)
+    hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for(n * lda, 256, 4096)), dim3(256), 0, s,
+                       (const T *)B2, dinv, 1.0, B2, n, lda);
+  T *Y = B1;
+  if (k == 0) {
+    // degree 0: Y = P_1 / theta_1
+    hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for(n * lda, 256, 4096)), dim3(256), 0, s,
+                       (const T *)B2, (const double *)nullptr, 1.0 / roots[0], Y, n, lda);
+  }
+  T *Pa = B2, *Pb = spare;
+  for (int i = 0; i < k; ++i) {
+    EpiPolyP<T> e;
+    e.Yin = i == 0 ? nullptr : Y;
+    e.Yout = Y;
+    e.Pout = Pb;
+    e.ld = lda;
+    e.inv_t = 1.0 / roots[i];
+    e.inv_t_next = 1.0 / roots[i + 1];
+    e.dinv = dinv;
+    e.last = i == k - 1 ? 1 : 0;
+    const double bytes = (i == 0 || i == k - 1) ? b3 : b4;
+    int id = h->plog.begin(PH_PRECOND, bytes, s);
+    int st = vspmm_poly<T>(g, plan, Pa, lda, na, e, s);
+    h->plog.end(id, s);
+    ++*calls;
+    ++*pcalls;
+    SPHX_TRY(st);
+    std::swap(Pa, Pb);
+  }
+  // back to the padded layout (B2 or spare is free: expand into the one
+  // that does not hold Y)
+  T *dst = (Y == B2) ? spare : B2;
+  hipLaunchKernelGGL(k_expand_cols<T>, dim3(grid_for(n * na, 256, 4096)), dim3(256), 0, s,
+                     (const T *)Y, lda, cm, dst, ld, n);
+  *result = dst;
+  return SPHX_OK;
+}
+
 // The LOBPCG solve (Algorithm 1) in precision T; fills eigvals / vecs.
 template <typename T>
 int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const void *X0,
@@ -383,11 +452,27 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   if (o.precond == SPHX_PRECOND_CHEBYSHEV) {
     double hi = gen ? 2.0 : 2.0 * ds.max_wdeg;
     ck = cheb_coef(o.cheb_degree, hi / o.cheb_ratio, hi);
-    if (gen) {
-      hipLaunchKernelGGL(k_inverse, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, w.d64,
-                         w.dinv, n);
-      dinv = w.dinv;
-    }
+  }
+  if ((o.precond == SPHX_PRECOND_CHEBYSHEV || o.precond == SPHX_PRECOND_GMRES) && gen) {
+    hipLaunchKernelGGL(k_inverse, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, w.d64, w.dinv,
+                       n);
+    dinv = w.dinv;
+  }
+  // GMRES polynomial: roots from a seeded start vector (in y for the
+  // normalized problem, mapped to x = D^-1/2 y)
+  double roots[kMaxW];
+  int nroots = 0;
+  if (o.precond == SPHX_PRECOND_GMRES) {
+    launch_init_random<double>(w.poly_b, n, 1, 1, o.seed ^ 0x9e3779b97f4a7c15ull, s);
+    if (norm)
+      hipLaunchKernelGGL(k_scale_rows<double>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s,
+                         (const double *)w.poly_b, (const double *)w.rsq, 1.0, w.poly_b, n, 1);
+    std::string err;
+    int id = pl.begin(PH_SETUP, 0.0, s);
+    int r = poly_roots(g, w.plan, gen, w.d64, dinv, w.poly_b, o.cheb_degree, roots, &nroots,
+                       w.poly_scratch, h->pinned_small, s, &err);
+    pl.end(id, s);
+    if (r != SPHX_OK) return set_err(h, r, err);
   }
   if (stats) {
     stats->max_degree = ds.max_deg;
@@ -457,6 +542,9 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     if (o.precond == SPHX_PRECOND_CHEBYSHEV) {
       SPHX_TRY(cheb_apply<T>(h, g, w.plan, m, ld, act, w.R, w.B1, w.B2, w.R, ck, dinv, s, &H,
                              &calls, &pcalls));
+    } else if (o.precond == SPHX_PRECOND_GMRES) {
+      SPHX_TRY(poly_apply<T>(h, g, w.plan, m, ld, act, w.R, w.B1, w.B2, w.R, roots, nroots,
+                             dinv, s, &H, &calls, &pcalls));
     } else if (o.precond == SPHX_PRECOND_NONE) {
       H = w.R;
     }
@@ -619,8 +707,8 @@ void sphx_options_default(sphx_options *o, int regular, int precond) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
   o->precond = precond;
-  o->problem = regular ? SPHX_COMBINATORIAL
-                       : (precond == SPHX_PRECOND_CHEBYSHEV ? SPHX_NORMALIZED : SPHX_GENERALIZED);
+  const bool poly = precond == SPHX_PRECOND_CHEBYSHEV || precond == SPHX_PRECOND_GMRES;
+  o->problem = regular ? SPHX_COMBINATORIAL : (poly ? SPHX_NORMALIZED : SPHX_GENERALIZED);
   o->tol = regular ? 1e-3 : 1e-2;
   o->init = regular ? SPHX_INIT_RANDOM : SPHX_INIT_PIECEWISE;
   o->cheb_degree = 25;
@@ -696,16 +784,21 @@ int sphx_graph_info(sphx_handle *h, sphx_graph *g, int *is_regular, int64_t *max
   return SPHX_OK;
 }
 
-static size_t solve_bytes(sphx_graph *g, int nev, int precision, int K, bool split) {
+static int poly_degree_of(const sphx_options *o) {
+  return o->precond == SPHX_PRECOND_GMRES ? o->cheb_degree : 0;
+}
+
+static size_t solve_bytes(sphx_graph *g, int nev, int precision, int K, bool split,
+                          int poly_degree) {
   Arena a;
   a.count_only = true;
   size_t pb = plan_bytes(g);
   if (precision == SPHX_MIXED) {
     SolveWs<float> w;
-    layout(a, w, g->n, nev, K, pb, split);
+    layout(a, w, g->n, nev, K, pb, split, poly_degree);
   } else {
     SolveWs<double> w;
-    layout(a, w, g->n, nev, K, pb, split);
+    layout(a, w, g->n, nev, K, pb, split, poly_degree);
   }
   return a.off + 4096;
 }
@@ -714,7 +807,7 @@ int sphx_workspace_size(sphx_handle *h, sphx_graph *g, int nev, const sphx_optio
                         size_t *bytes) {
   if (!h || !g || !opt || !bytes || nev < 1 || nev > kMaxNev) return SPHX_E_INVALID_ARG;
   int K = 1 << (nev - 1);
-  size_t a = solve_bytes(g, nev, opt->precision, K, true);
+  size_t a = solve_bytes(g, nev, opt->precision, K, true, poly_degree_of(opt));
   size_t b = adjoint_scratch_bytes(g->n, nev) + plan_bytes(g) + sizeof(double) * 2 * g->n +
              4096;
   *bytes = std::max(a, b);
@@ -835,6 +928,10 @@ int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int
     else
       hipLaunchKernelGGL(k_jacobi<double>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s,
                          (const double *)R, d64, (double *)H, n, m);
+  } else if (o->precond == SPHX_PRECOND_GMRES) {
+    return set_err(h, SPHX_E_INVALID_ARG,
+                   "the GMRES polynomial is applied with sphx_poly_apply (roots from "
+                   "sphx_poly_roots)");
   } else {
     const bool gen = o->problem != SPHX_COMBINATORIAL;
     if (gen && !(ds.min_wdeg > 0)) return set_err(h, SPHX_E_INVALID_ARG, "isolated vertex");
@@ -887,6 +984,121 @@ int sphx_precond_apply(sphx_handle *h, sphx_graph *g, const sphx_options *o, int
   return SPHX_OK;
 }
 
+int sphx_poly_roots(sphx_handle *h, sphx_graph *g, int problem, int degree, const double *b,
+                    double *roots, int *nroots) {
+  if (!h || !g || !b || !roots || !nroots || degree < 1 || degree + 1 > kMaxW ||
+      (problem != SPHX_COMBINATORIAL && problem != SPHX_GENERALIZED &&
+       problem != SPHX_NORMALIZED))
+    return SPHX_E_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  hipStream_t s = h->stream;
+  const int64_t n = g->n;
+  size_t need = plan_bytes(g) + 5 * align_up(sizeof(double) * n, 256) +
+                align_up(4 * kDegBlocksMax * sizeof(double), 256) +
+                poly_scratch_bytes(n, degree) + 4096;
+  char *ws = nullptr;
+  SPHX_TRY(get_workspace(h, need, &ws));
+  Arena a;
+  a.base = ws;
+  double *d64 = a.take<double>(n);
+  double *dinv = a.take<double>(n);
+  double *sq = a.take<double>(n);
+  double *rsq = a.take<double>(n);
+  double *bx = a.take<double>(n);
+  double *degs = a.take<double>(4 * kDegBlocksMax);
+  char *scr = a.take<char>(poly_scratch_bytes(n, degree));
+  DegreeStats ds;
+  SPHX_TRY(compute_degrees(g, d64, nullptr, degs, &ds, h->pinned_small, s));
+  SpmmPlan plan;
+  SPHX_TRY(build_plan(g, a, &plan, ds, h->pinned_small, s));
+  const bool gen = problem != SPHX_COMBINATORIAL;
+  if (gen && !(ds.min_wdeg > 0)) return set_err(h, SPHX_E_INVALID_ARG, "isolated vertex");
+  hipLaunchKernelGGL(k_inverse, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, d64, dinv, n);
+  const double *bb = b;
+  if (problem == SPHX_NORMALIZED) {   // b is given in y; x = D^-1/2 y
+    hipLaunchKernelGGL(k_sqrt_pair, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, d64, sq, rsq,
+                       n);
+    hipLaunchKernelGGL(k_scale_rows<double>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, b,
+                       (const double *)rsq, 1.0, bx, n, 1);
+    bb = bx;
+  }
+  std::string err;
+  int r = poly_roots(g, plan, gen, d64, gen ? dinv : nullptr, bb, degree, roots, nroots, scr,
+                     h->pinned_small, s, &err);
+  if (r != SPHX_OK) return set_err(h, r, err);
+  return SPHX_OK;
+}
+
+int sphx_poly_apply(sphx_handle *h, sphx_graph *g, int problem, int nroots,
+                    const double *roots, int m, int dtype, const void *R, void *H) {
+  if (!h || !g || !roots || !R || !H || nroots < 1 || nroots > kMaxW || m < 1 ||
+      m > kMaxNev || (dtype != SPHX_F32 && dtype != SPHX_F64) ||
+      (problem != SPHX_COMBINATORIAL && problem != SPHX_GENERALIZED &&
+       problem != SPHX_NORMALIZED))
+    return SPHX_E_INVALID_ARG;
+  for (int i = 0; i < nroots; ++i)
+    if (!(roots[i] != 0.0) || !std::isfinite(roots[i]))
+      return set_err(h, SPHX_E_INVALID_ARG, "polynomial roots must be finite and non-zero");
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  hipStream_t s = h->stream;
+  const int64_t n = g->n;
+  const int es = bytes_of(dtype);
+  const int wd = std::max(m, compact_ld(m));   // widest row the buffers must hold
+  const size_t blk = (size_t)n * wd * es;
+  size_t need = plan_bytes(g) + 4 * align_up(sizeof(double) * n, 256) +
+                align_up(4 * kDegBlocksMax * sizeof(double), 256) + 4 * align_up(blk, 256) +
+                4096;
+  char *ws = nullptr;
+  SPHX_TRY(get_workspace(h, need, &ws));
+  Arena a;
+  a.base = ws;
+  double *d64 = a.take<double>(n);
+  double *dinv = a.take<double>(n);
+  double *sq = a.take<double>(n);
+  double *rsq = a.take<double>(n);
+  double *degs = a.take<double>(4 * kDegBlocksMax);
+  char *b0 = a.take<char>(blk);
+  char *b1 = a.take<char>(blk);
+  char *b2 = a.take<char>(blk);
+  char *b3 = a.take<char>(blk);
+  DegreeStats ds;
+  SPHX_TRY(compute_degrees(g, d64, nullptr, degs, &ds, h->pinned_small, s));
+  SpmmPlan plan;
+  SPHX_TRY(build_plan(g, a, &plan, ds, h->pinned_small, s));
+  const bool gen = problem != SPHX_COMBINATORIAL;
+  const bool norm = problem == SPHX_NORMALIZED;
+  if (gen && !(ds.min_wdeg > 0)) return set_err(h, SPHX_E_INVALID_ARG, "isolated vertex");
+  hipLaunchKernelGGL(k_inverse, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, d64, dinv, n);
+  if (norm)
+    hipLaunchKernelGGL(k_sqrt_pair, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, d64, sq, rsq,
+                       n);
+  ColMap cm = identity_map(m);
+  int64_t calls = 0, pcalls = 0;
+  h->plog.reset();
+  h->plog.on = false;
+  auto go = [&](auto tag) -> int {
+    using T = decltype(tag);
+    const T *src = static_cast<const T *>(R);
+    if (norm) {   // p(L_N) r = D^1/2 [p(D^-1 L) D^-1] (D^1/2 r)
+      hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s,
+                         src, (const double *)sq, 1.0, (T *)b0, n, m);
+      src = (const T *)b0;
+    }
+    T *res = nullptr;
+    SPHX_TRY(poly_apply<T>(h, g, plan, m, m, cm, src, (T *)b1, (T *)b2, (T *)b3, roots, nroots,
+                           gen ? dinv : nullptr, s, &res, &calls, &pcalls));
+    if (norm)
+      hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for(n * m, 256, 4096)), dim3(256), 0, s,
+                         (const T *)res, (const double *)sq, 1.0, (T *)H, n, m);
+    else
+      SPHX_HIP(h, hipMemcpyAsync(H, res, sizeof(T) * n * m, hipMemcpyDeviceToDevice, s));
+    return SPHX_OK;
+  };
+  SPHX_TRY(dtype == SPHX_F32 ? go(float{}) : go(double{}));
+  SPHX_HIP(h, hipGetLastError());
+  return SPHX_OK;
+}
+
 static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_options *o,
                            const void *X0, double *eigvals, void *eigvecs, int K,
                            int32_t *part, double *cut, double *imbalance,
@@ -902,7 +1114,8 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
   h->plog.on = h->timing && stats;
   const bool split = part != nullptr;
   char *ws = nullptr;
-  SPHX_TRY(get_workspace(h, solve_bytes(g, nev, o->precision, std::max(K, 1), split), &ws));
+  SPHX_TRY(get_workspace(
+      h, solve_bytes(g, nev, o->precision, std::max(K, 1), split, poly_degree_of(o)), &ws));
   bool hit_max = false;
   int st;
   auto run = [&](auto tag) -> int {
@@ -910,7 +1123,7 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
     Arena a;
     a.base = ws;
     SolveWs<T> w;
-    layout(a, w, g->n, nev, std::max(K, 1), plan_bytes(g), split);
+    layout(a, w, g->n, nev, std::max(K, 1), plan_bytes(g), split, poly_degree_of(o));
     T *vecs = eigvecs ? static_cast<T *>(eigvecs) : w.V;
     if (!vecs) return set_err(h, SPHX_E_INVALID_ARG, "eigvecs is NULL");
     SPHX_TRY(solve<T>(h, g, nev, *o, X0, eigvals, vecs, stats, w, ws, &hit_max));

@@ -498,6 +498,108 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
   }
 }
 
+// --------------------------------------------------- polynomial roots
+// Harmonic Ritz values of a Lanczos projection (the roots of the GMRES
+// residual polynomial): H is (k1 + 1) x k1 row-major (stride k1).  They are
+// the eigenvalues of the pencil (H^T H, H_k) with H_k the leading k1 x k1
+// block (symmetrised): H_k = L L^T (Cholesky), C = L^-1 H^T H L^-T, cyclic
+// Jacobi.  The roots are written in modified Leja order: the largest first,
+// then each maximising the sum of log distances to those already chosen
+// (lowest index on ties).  status: 0, or 1 if H_k is not positive definite.
+__global__ __launch_bounds__(256) void k_harmonic_ritz(const double *__restrict__ Hg, int k1,
+                                                       double *theta, int *status) {
+  __shared__ double Mk[kMaxW * LDA], Mc[kMaxW * LDA], Mv[kMaxW * LDA];
+  __shared__ double lam[kMaxW];
+  __shared__ double pc[kMaxW / 2 + 1], ps[kMaxW / 2 + 1];
+  __shared__ int pp[kMaxW / 2 + 1], pq[kMaxW / 2 + 1];
+  __shared__ int changed, bad;
+  const int t = threadIdx.x;
+  // Mk = sym(H_k), Mc = H^T H
+  for (int e = t; e < k1 * k1; e += blockDim.x) {
+    const int i = e / k1, j = e - i * k1;
+    Mk[i * LDA + j] = 0.5 * (Hg[i * k1 + j] + Hg[j * k1 + i]);
+    double sum = 0.0;
+    for (int r = 0; r <= k1; ++r) sum += Hg[r * k1 + i] * Hg[r * k1 + j];
+    Mc[i * LDA + j] = sum;
+  }
+  if (t == 0) bad = 0;
+  __syncthreads();
+  // Cholesky of Mk in place (lower), one thread
+  if (t == 0) {
+    for (int j = 0; j < k1 && !bad; ++j) {
+      double d = Mk[j * LDA + j];
+      for (int q = 0; q < j; ++q) d -= Mk[j * LDA + q] * Mk[j * LDA + q];
+      if (!(d > 0.0)) { bad = 1; break; }
+      d = sqrt(d);
+      Mk[j * LDA + j] = d;
+      for (int i = j + 1; i < k1; ++i) {
+        double v = Mk[i * LDA + j];
+        for (int q = 0; q < j; ++q) v -= Mk[i * LDA + q] * Mk[j * LDA + q];
+        Mk[i * LDA + j] = v / d;
+      }
+    }
+  }
+  __syncthreads();
+  if (bad) {
+    if (t == 0) *status = 1;
+    return;
+  }
+  // T = L^-1 Mc (column per thread) -> Mv
+  if (t < k1) {
+    for (int i = 0; i < k1; ++i) {
+      double v = Mc[i * LDA + t];
+      for (int q = 0; q < i; ++q) v -= Mk[i * LDA + q] * Mv[q * LDA + t];
+      Mv[i * LDA + t] = v / Mk[i * LDA + i];
+    }
+  }
+  __syncthreads();
+  // C = L^-1 T^T (column c has right-hand side row c of T) -> Mc
+  if (t < k1) {
+    for (int i = 0; i < k1; ++i) {
+      double v = Mv[t * LDA + i];
+      for (int q = 0; q < i; ++q) v -= Mk[i * LDA + q] * Mc[q * LDA + t];
+      Mc[i * LDA + t] = v / Mk[i * LDA + i];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < k1 * k1; e += blockDim.x) {
+    const int i = e / k1, j = e - i * k1;
+    if (i < j) {
+      const double v = 0.5 * (Mc[i * LDA + j] + Mc[j * LDA + i]);
+      Mc[i * LDA + j] = v;
+      Mc[j * LDA + i] = v;
+    }
+  }
+  __syncthreads();
+  jacobi_eig(Mc, Mv, k1, pc, ps, pp, pq, &changed);
+  if (t < k1) lam[t] = Mc[t * LDA + t];
+  __syncthreads();
+  if (t == 0) {
+    bool used[kMaxW];
+    for (int i = 0; i < k1; ++i) used[i] = false;
+    int first = 0;
+    for (int i = 1; i < k1; ++i)
+      if (fabs(lam[i]) > fabs(lam[first])) first = i;
+    theta[0] = lam[first];
+    used[first] = true;
+    double score[kMaxW];
+    for (int i = 0; i < k1; ++i) score[i] = 0.0;
+    int last = first;
+    for (int q = 1; q < k1; ++q) {
+      int best = -1;
+      for (int i = 0; i < k1; ++i) {
+        if (used[i]) continue;
+        score[i] += log(fabs(lam[i] - lam[last]));
+        if (best < 0 || score[i] > score[best]) best = i;
+      }
+      theta[q] = lam[best];
+      used[best] = true;
+      last = best;
+    }
+    *status = 0;
+  }
+}
+
 // --------------------------------------------------------------- update
 struct UpdDev {
   int64_t n;
@@ -828,6 +930,11 @@ int gram(const T *X, const T *LX, const T *H, const T *LH, const T *P, const T *
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ceil_div(2 * W * W, 16)), dim3(256), 0, s,
                      (const double *)partials, nb, NT, gram_out);
   return hipGetLastError() == hipSuccess ? SPHX_OK : SPHX_E_HIP;
+}
+
+void launch_harmonic_ritz(const double *H, int k1, double *theta, int *status,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_harmonic_ritz, dim3(1), dim3(256), 0, s, H, k1, theta, status);
 }
 
 void launch_rr(const double *gram_out, const RRArgs &a, double *Y, double *theta,

@@ -66,6 +66,21 @@ struct EpiResidualP {
   int generalized;
   int jacobi;
 };
+// One step of the GMRES-polynomial apply (product form over the roots):
+//   Y <- Y + P / theta_i  (Y = 0 on the first step),
+//   P' = P - s (L P) / theta_i  (s = 1 / d_i for the generalized problem),
+// and on the last step Y <- Y + P' / theta_{k+1} instead of storing P'.
+template <typename T>
+struct EpiPolyP {
+  const T *Yin;        // nullable on the first step
+  T *Yout;
+  T *Pout;             // unused on the last step
+  int ld;
+  double inv_t, inv_t_next;
+  const double *dinv;  // nullable: 1
+  int last;
+};
+
 template <typename T>
 struct EpiChebP {
   const T *prev;       // previous iterate is prev_scale * prev (nullable = 0)
@@ -108,6 +123,9 @@ int vspmm_residual(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int 
 template <typename T>
 int vspmm_cheb(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
                EpiChebP<T> epi, hipStream_t s);
+template <typename T>
+int vspmm_poly(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
+               EpiPolyP<T> epi, hipStream_t s);
 
 // ------------------------------------------------------------------ dense
 // Initial blocks (n x ld, columns >= m zero).
@@ -145,6 +163,16 @@ struct RRArgs {
 };
 void launch_rr(const double *gram_out, const RRArgs &a, double *Y, double *theta,
                DevStatus *st, hipStream_t s);
+// GMRES polynomial (poly.hip): scratch bytes, and the roots (Leja order)
+// from start vector b (x variables; B-inner product D if gen).
+size_t poly_scratch_bytes(int64_t n, int degree);
+int poly_roots(sphx_graph *g, const SpmmPlan &plan, bool gen, const double *d64,
+               const double *dinv, const double *b, int degree, double *roots, int *nroots,
+               void *scratch, void *pinned, hipStream_t s, std::string *err);
+// Roots of the GMRES residual polynomial from a (k1 + 1) x k1 Lanczos
+// projection (k1 <= kMaxW), modified Leja order; status 1 if H_k is not SPD.
+void launch_harmonic_ritz(const double *H, int k1, double *theta, int *status,
+                          hipStream_t s);
 
 // X <- [X, H_a, P_a] Y ; P <- [0, H_a, P_a] Y ; LP <- [0, LH_a, LP_a] Y
 struct UpdateArgs {

@@ -188,6 +188,36 @@ struct VCheb {
   }
 };
 
+template <typename T, int VB, int NV>
+struct VPoly {
+  EpiPolyP<T> p;
+  static constexpr bool kNorms = false;
+  using V = typename Vec<T, VB>::type;
+  static constexpr int E = Vec<T, VB>::E;
+  __device__ void row(int64_t i, const V (&xi)[NV], const V (&acc)[NV], double *, double *) const {
+    const double si = p.dinv ? p.dinv[i] : 1.0;
+    const V *yi = p.Yin ? reinterpret_cast<const V *>(p.Yin + i * p.ld) : nullptr;
+    V *yo = reinterpret_cast<V *>(p.Yout + i * p.ld);
+    V *po = p.last ? nullptr : reinterpret_cast<V *>(p.Pout + i * p.ld);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const V y0 = yi ? yi[v] : V(0);
+      V y, pn;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const double pv = double(xi[v][e]);
+        const double pnew = pv - si * double(acc[v][e]) * p.inv_t;
+        double yv = double(y0[e]) + pv * p.inv_t;
+        if (p.last) yv += pnew * p.inv_t_next;
+        y[e] = T(yv);
+        pn[e] = T(pnew);
+      }
+      yo[v] = y;
+      if (po) po[v] = pn;
+    }
+  }
+};
+
 // Per-column block sums of the thread norms (columns < m), fixed order:
 // butterfly within each wavefront, then the 4 wavefronts in order.
 template <int LD>
@@ -517,13 +547,21 @@ int vspmm_cheb(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
   return dispatch_nv<T, VCheb>(g, plan, X, ld, epi, m, nullptr, nullptr, s);
 }
 
+template <typename T>
+int vspmm_poly(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
+               EpiPolyP<T> epi, hipStream_t s) {
+  return dispatch_nv<T, VPoly>(g, plan, X, ld, epi, m, nullptr, nullptr, s);
+}
+
 #define SPHX_VINST(T)                                                                       \
   template int vspmm_store<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,         \
                               EpiStoreP<T>, hipStream_t);                                  \
   template int vspmm_residual<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,      \
                                  EpiResidualP<T>, double *, int *, hipStream_t);           \
   template int vspmm_cheb<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,          \
-                             EpiChebP<T>, hipStream_t);
+                             EpiChebP<T>, hipStream_t);                                    \
+  template int vspmm_poly<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,          \
+                             EpiPolyP<T>, hipStream_t);
 SPHX_VINST(float)
 SPHX_VINST(double)
 #undef SPHX_VINST

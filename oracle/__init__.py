@@ -15,15 +15,17 @@ Modules
                Laplacian, graph classification, residual norm
   eigen      - number of eigenvectors (Eq. 4), dense smallest eigenpairs (the
                plain definition), Rayleigh-Ritz, LOBPCG (Algorithm 1)
-  precond    - Jacobi and Chebyshev preconditioner applies (Section 5)
-  split      - coordinate split into K = 2^m parts (Algorithm 2, multi-jagged
-               special case)
+  precond    - Jacobi, Chebyshev and GMRES-polynomial preconditioners
+               (Section 5)
+  split      - coordinate split into K parts (Algorithm 2, multi-jagged)
   quality    - cutsize (Eq. 1), part weights and imbalance (Section 3.1)
   adjoint    - derivative of eigenvalues / eigenvectors with respect to edge
                weights (dense full-basis reference and projected solve)
+  refine     - greedy refinement of a K-way partition under the balance
+               constraint (Sec. 7, Sec. 3.1)
 
 Pins: every function is checked in tests/test_oracle_*.py against closed forms,
 library special cases, invariants or brute force.  No function here is
 "parity unpinned".
 """
-from . import laplacian, eigen, precond, split, quality, adjoint  # noqa: F401
+from . import laplacian, eigen, precond, split, quality, adjoint, refine  # noqa: F401

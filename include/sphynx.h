@@ -254,6 +254,35 @@ int sphx_quality(sphx_handle *h, sphx_graph *g, const int32_t *part, int K,
                  double *cut, double *cut2x, double *imbalance,
                  int64_t *part_weights);
 
+/* Greedy refinement of a K-way partition (Sec. 7 proposes a greedy
+ * improvement step for the cut of the spectral partition; balance as in
+ * Sec. 3.1: every part weight W_k below W_avg (1 + eps), eps = 0.01 in the
+ * experiments of Sec. 6).  One pass:
+ *  1. each vertex v of degree 1..2048 in part a targets the neighbour part
+ *     t != a with the largest edge weight conn(v, t) from v (smallest t on
+ *     ties); gain g = conn(v, t) - conn(v, a); candidates have g > 0;
+ *  2. candidates are ranked by (g descending, id ascending); v remains a
+ *     mover when its gain, with every higher-ranked candidate at its target,
+ *     stays positive;
+ *  3. the movers into part p, in increasing id, are accepted while W_p plus
+ *     their cumulative weight stays <= C, C the largest integer below
+ *     (W / K)(1 + eps) (departures are not credited);
+ *  4. accepted movers take their targets.
+ * A pass is kept only when the exact cut drops; passes repeat while it does,
+ * at most max_passes.  All sums are exact (float weights in 128-bit fixed
+ * point, ratio of weights at most 2^40), so the result does not depend on
+ * the order of the additions.
+ * part: device int32[n] with values in [0, K), refined in place.
+ * eps >= 0.  cut, imbalance (host, may be NULL): of the returned partition,
+ * as in sphx_quality.  passes (host, may be NULL): passes kept.  moves
+ * (host, may be NULL): accepted moves over the kept passes.
+ * Warm-start repartitioning (Sec. 1: partitions recomputed as the data
+ * changes, on the accelerator) passes the previous eigenvectors as X0 with
+ * SPHX_INIT_USER to sphx_partition and may refine its part vector here. */
+int sphx_refine(sphx_handle *h, sphx_graph *g, int K, int32_t *part,
+                double eps, int max_passes, double *cut, double *imbalance,
+                int *passes, int64_t *moves);
+
 /* Algorithm 2 end to end: nev = d = floor(log2 K) + 1 eigenpairs, the
  * embedding = eigenvector columns 1..d-1 (the trivial one dropped), the
  * split into any 2 <= K <= n parts and its quality.  eigvals host double[d]; eigvecs device n x d (as

@@ -79,6 +79,8 @@ def _load():
                                       C.POINTER(_Stats)]),
         "sphx_split": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, vp]),
         "sphx_quality": (C.c_int, [vp, vp, vp, C.c_int, dp, dp, dp, C.POINTER(C.c_int64)]),
+        "sphx_refine": (C.c_int, [vp, vp, C.c_int, vp, C.c_double, C.c_int, dp, dp,
+                                  C.POINTER(C.c_int), C.POINTER(C.c_int64)]),
         "sphx_partition": (C.c_int, [vp, vp, C.c_int, C.POINTER(_Options), vp, dp, vp, vp,
                                      dp, dp, C.POINTER(_Stats)]),
         "sphx_eig_backward": (C.c_int, [vp, vp, C.c_int, C.c_int, dp, vp, dp, vp, C.c_double,
@@ -382,6 +384,21 @@ def quality(h: Handle, g: Graph, part, K: int):
     h._check(lib.sphx_quality(h.h, g.g, C.c_void_p(_ptr(part)), K, C.byref(cut),
                               C.byref(cut2), C.byref(imb), pw))
     return cut.value, cut2.value, imb.value, list(pw)
+
+
+def refine(h: Handle, g: Graph, part, K: int, eps: float = 0.01, max_passes: int = 8):
+    """Greedy refinement of the device int32 part vector, in place:
+    (cut, imbalance, passes kept, accepted moves)."""
+    torch = _torch()
+    if part.dtype != torch.int32 or not part.is_contiguous():
+        raise ValueError("part must be a contiguous int32 tensor (refined in place)")
+    cut = C.c_double()
+    imb = C.c_double()
+    passes = C.c_int()
+    moves = C.c_int64()
+    h._check(lib.sphx_refine(h.h, g.g, K, C.c_void_p(_ptr(part)), float(eps), int(max_passes),
+                             C.byref(cut), C.byref(imb), C.byref(passes), C.byref(moves)))
+    return cut.value, imb.value, passes.value, moves.value
 
 
 def partition(h: Handle, g: Graph, K: int, opts: Options, X0=None,

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libsphynx.so")
 ARCH = "gfx950"
 
 SOURCES = ["spmm.hip", "spmm_vec.hip", "setup.hip", "dense.hip", "split.hip", "quality.hip",
-           "adjoint.hip", "poly.hip", "capi.hip"]
+           "adjoint.hip", "poly.hip", "refine.hip", "capi.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

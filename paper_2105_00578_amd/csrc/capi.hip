@@ -276,13 +276,18 @@ int cheb_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, int l
   const int wd = compact ? lda : ld;     // row width of the iteration buffers
   const int mm = compact ? na : m;
   auto launch = [&](const T *src, EpiChebP<T> e, double bytes) -> int {
-    int id = h->plog.begin(PH_PRECOND, bytes, s);
     // padded rows (the solver's blocks) take the vector-row kernels; the
     // column-lane kernels serve unpadded caller blocks
-    int st = compact || ld != m || (m * (int)sizeof(T)) % 16 == 0
-                 ? vspmm_cheb<T>(g, plan, src, wd, mm, e, s)
-                 : spmm_cheb<T>(g, plan, src, m, cm, e, s);
-    h->plog.end(id, s);
+    int st;
+    if (compact || ld != m || (m * (int)sizeof(T)) % 16 == 0) {
+      LaunchEvents ev;
+      const bool timed = h->plog.begin_stamped(PH_PRECOND, bytes, &ev.start, &ev.stop);
+      st = vspmm_cheb<T>(g, plan, src, wd, mm, e, s, timed ? &ev : nullptr);
+    } else {
+      int id = h->plog.begin(PH_PRECOND, bytes, s);
+      st = spmm_cheb<T>(g, plan, src, m, cm, e, s);
+      h->plog.end(id, s);
+    }
     ++*calls;
     ++*pcalls;
     return st;
@@ -397,9 +402,9 @@ int poly_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, int l
     e.dinv = dinv;
     e.last = i == k - 1 ? 1 : 0;
     const double bytes = (i == 0 || i == k - 1) ? b3 : b4;
-    int id = h->plog.begin(PH_PRECOND, bytes, s);
-    int st = vspmm_poly<T>(g, plan, Pa, lda, na, e, s);
-    h->plog.end(id, s);
+    LaunchEvents ev;
+    const bool timed = h->plog.begin_stamped(PH_PRECOND, bytes, &ev.start, &ev.stop);
+    int st = vspmm_poly<T>(g, plan, Pa, lda, na, e, s, timed ? &ev : nullptr);
     ++*calls;
     ++*pcalls;
     SPHX_TRY(st);
@@ -1231,6 +1236,30 @@ int sphx_quality(sphx_handle *h, sphx_graph *g, const int32_t *part, int K, doub
   if (r != SPHX_OK) return set_err(h, r, err);
   if (cut) *cut = c;
   if (cut2x) *cut2x = 2.0 * c;
+  return SPHX_OK;
+}
+
+int sphx_refine(sphx_handle *h, sphx_graph *g, int K, int32_t *part, double eps,
+                int max_passes, double *cut, double *imbalance, int *passes,
+                int64_t *moves) {
+  if (!h || !g || !part || K < 1 || max_passes < 0 || !(eps >= 0.0) || !std::isfinite(eps))
+    return SPHX_E_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  if (g->wdt != SPHX_UNIT && !g->stats_valid) {
+    size_t need = align_up(sizeof(double) * g->n, 256) + 4 * kDegBlocksMax * sizeof(double) + 512;
+    char *ws = nullptr;
+    SPHX_TRY(get_workspace(h, need, &ws));
+    DegreeStats ds;
+    SPHX_TRY(compute_degrees(g, reinterpret_cast<double *>(ws), nullptr,
+                             ws + align_up(sizeof(double) * g->n, 256), &ds, h->pinned_small,
+                             h->stream));
+  }
+  char *ws = nullptr;
+  SPHX_TRY(get_workspace(h, refine_scratch_bytes(g->n, K), &ws));
+  std::string err;
+  int r = refine(g, part, K, eps, max_passes, cut, imbalance, passes, moves, ws,
+                 h->pinned_small, h->stream, &err);
+  if (r != SPHX_OK) return set_err(h, r, err);
   return SPHX_OK;
 }
 

@@ -78,6 +78,17 @@ struct PhaseLog {
   void end(int id, hipStream_t s) {
     if (id >= 0) (void)hipEventRecord(recs[id].b, s);
   }
+  // a launch group whose kernels record the two events themselves; false
+  // when timing is off
+  bool begin_stamped(int phase, double bytes, hipEvent_t *a, hipEvent_t *b) {
+    if (!on) return false;
+    Rec r{phase, bytes, take(), take()};
+    if (!r.a || !r.b) return false;
+    recs.push_back(r);
+    *a = r.a;
+    *b = r.b;
+    return true;
+  }
   ~PhaseLog() {
     for (auto e : pool) (void)hipEventDestroy(e);
   }

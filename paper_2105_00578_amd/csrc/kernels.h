@@ -113,6 +113,14 @@ int spmm_cheb(sphx_graph *g, const SpmmPlan &plan, const T *X, int ldx,
 // Padded blocks: n x ld with ld * sizeof(T) a multiple of 16 bytes (columns
 // m..ld-1 are padding).  Thread-per-row products with 16-byte vector loads.
 int padded_ld(int m, int elem_bytes);
+
+// Events that bracket the kernels of one product: a single launch is stamped
+// by its own dispatch (start and end of execution); several launches are
+// bracketed by stream records.
+struct LaunchEvents {
+  hipEvent_t start, stop;
+};
+
 template <typename T>
 int vspmm_store(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
                 EpiStoreP<T> epi, hipStream_t s);
@@ -122,10 +130,10 @@ int vspmm_residual(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int 
                    hipStream_t s);
 template <typename T>
 int vspmm_cheb(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
-               EpiChebP<T> epi, hipStream_t s);
+               EpiChebP<T> epi, hipStream_t s, const LaunchEvents *ev = nullptr);
 template <typename T>
 int vspmm_poly(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
-               EpiPolyP<T> epi, hipStream_t s);
+               EpiPolyP<T> epi, hipStream_t s, const LaunchEvents *ev = nullptr);
 
 // ------------------------------------------------------------------ dense
 // Initial blocks (n x ld, columns >= m zero).
@@ -224,9 +232,18 @@ int split_mj(sphx_graph *g, const T *coords, int ld, int ncoord, int K,
 
 // ---------------------------------------------------------------- quality
 size_t quality_scratch_bytes(int K);
+// cut_fixed (optional): the exact cut as an integer multiple of 2^e0 (unit
+// weights: the number of cut edges), for exact comparisons
 int quality(sphx_graph *g, const int32_t *part, int K, double *cut,
             double *imbalance, int64_t *part_weights, void *scratch,
-            void *pinned, hipStream_t s, std::string *err);
+            void *pinned, hipStream_t s, std::string *err,
+            unsigned __int128 *cut_fixed = nullptr);
+
+// ----------------------------------------------------------------- refine
+size_t refine_scratch_bytes(int64_t n, int K);
+int refine(sphx_graph *g, int32_t *part, int K, double eps, int max_passes, double *cut,
+           double *imbalance, int *passes, int64_t *moves, void *scratch, void *pinned,
+           hipStream_t s, std::string *err);
 
 // ---------------------------------------------------------------- adjoint
 size_t adjoint_scratch_bytes(int64_t n, int nev);

@@ -117,7 +117,7 @@ size_t quality_scratch_bytes(int K) {
 
 int quality(sphx_graph *g, const int32_t *part, int K, double *cut, double *imbalance,
             int64_t *part_weights, void *scratch, void *pinned, hipStream_t s,
-            std::string *err) {
+            std::string *err, unsigned __int128 *cut_fixed) {
   Arena a;
   a.base = static_cast<char *>(scratch);
   unsigned long long *cp = a.take<unsigned long long>(2 * kCutBlocks);
@@ -172,6 +172,7 @@ int quality(sphx_graph *g, const int32_t *part, int K, double *cut, double *imba
   unsigned __int128 tot = 0;
   for (unsigned b = 0; b < nb; ++b)
     tot += ((unsigned __int128)hc[2 * b + 1] << 64) + hc[2 * b];
+  if (cut_fixed) *cut_fixed = tot;
   double c = u128_to_double(tot);
   if (g->wdt != SPHX_UNIT) c = std::ldexp(c, e0);
   if (cut) *cut = c;

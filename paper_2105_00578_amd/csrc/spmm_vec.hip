@@ -18,6 +18,8 @@
 // or the Jacobi step r / d_i, FP64 norm partials of ||r||^2_{B^-1} and
 // ||x||^2_B per column c < m), and one Chebyshev step of the iteration for
 // L h = r (Sec. 5.2).
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace sphx {
@@ -418,29 +420,34 @@ static_assert(kMaxShortBlocks <= kMaxNormBlocks && kGroupBlocks <= kMaxNormBlock
 
 template <typename T, int VB, int NV, typename IdxT, typename WT, typename Epi>
 void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X, int ld,
-             const Epi &epi, double *partials, int *nparts, int m, hipStream_t s) {
+             const Epi &epi, double *partials, int *nparts, int m, hipStream_t s,
+             const LaunchEvents *ev) {
   // Every launch writes one norm-partial slot per block: the grids below
   // stay within kMaxNormBlocks in total (grid-stride loops cover the rest).
   int used = 0;
+  // an unbinned plan is one launch, which ev (if given) times exactly
+  const bool stamp = ev && !plan.binned;
+  hipEvent_t e0 = stamp ? ev->start : nullptr, e1 = stamp ? ev->stop : nullptr;
+  if (ev && !stamp) (void)hipEventRecord(ev->start, s);
   auto short_rows = [&](const int32_t *rows, int64_t nr, int64_t maxb) {
     int64_t nb = ceil_div(nr, 256);
     int rpt = (int)ceil_div(nb, maxb);
     nb = ceil_div(nr, 256 * (int64_t)rpt);
-    hipLaunchKernelGGL((k_vrow<T, VB, NV, IdxT, WT, Epi>), dim3((unsigned)nb), dim3(256), 0, s,
-                       A, rows, nr, X, ld, rpt, epi, partials, used, m);
+    hipExtLaunchKernelGGL((k_vrow<T, VB, NV, IdxT, WT, Epi>), dim3((unsigned)nb), dim3(256), 0,
+                          s, e0, e1, 0, A, rows, nr, X, ld, rpt, epi, partials, used, m);
     used += (int)nb;
   };
   auto grouped = [&](int G, const int32_t *rows, int64_t nr, int64_t maxb) {
     unsigned gb = grid_for(nr, 256 / G, maxb);
     if (G == 4)
-      hipLaunchKernelGGL((k_vgroup<T, VB, NV, 4, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s, A,
-                         rows, nr, X, ld, epi, partials, used, m);
+      hipExtLaunchKernelGGL((k_vgroup<T, VB, NV, 4, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
+                            e0, e1, 0, A, rows, nr, X, ld, epi, partials, used, m);
     else if (G == 16)
-      hipLaunchKernelGGL((k_vgroup<T, VB, NV, 16, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
-                         A, rows, nr, X, ld, epi, partials, used, m);
+      hipExtLaunchKernelGGL((k_vgroup<T, VB, NV, 16, IdxT, WT, Epi>), dim3(gb), dim3(256), 0,
+                            s, e0, e1, 0, A, rows, nr, X, ld, epi, partials, used, m);
     else
-      hipLaunchKernelGGL((k_vgroup<T, VB, NV, 64, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
-                         A, rows, nr, X, ld, epi, partials, used, m);
+      hipExtLaunchKernelGGL((k_vgroup<T, VB, NV, 64, IdxT, WT, Epi>), dim3(gb), dim3(256), 0,
+                            s, e0, e1, 0, A, rows, nr, X, ld, epi, partials, used, m);
     used += (int)gb;
   };
   if (!plan.binned) {
@@ -464,12 +471,14 @@ void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X
       used += (int)gc;
     }
   }
+  if (ev && !stamp) (void)hipEventRecord(ev->stop, s);
   if (nparts) *nparts = used;
 }
 
 template <typename T, int VB, int NV, template <typename, int, int> class EpiT, typename P>
 int dispatch_types(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, const P &p,
-                   int m, double *partials, int *nparts, hipStream_t s) {
+                   int m, double *partials, int *nparts, hipStream_t s,
+                   const LaunchEvents *ev) {
   auto go = [&](auto idx_tag, auto w_tag) {
     using IdxT = decltype(idx_tag);
     using WT = decltype(w_tag);
@@ -477,7 +486,7 @@ int dispatch_types(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, cons
                     static_cast<const WT *>(g->w)};
     EpiT<T, VB, NV> epi{p};
     if constexpr (std::is_same_v<EpiT<T, VB, NV>, VResidual<T, VB, NV>>) epi.m = m;
-    run_vec<T, VB, NV>(A, g->n, plan, X, ld, epi, partials, nparts, m, s);
+    run_vec<T, VB, NV>(A, g->n, plan, X, ld, epi, partials, nparts, m, s, ev);
   };
   if (g->rp64) {
     if (g->wdt == SPHX_UNIT) go(int64_t{}, Unit{});
@@ -493,12 +502,13 @@ int dispatch_types(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, cons
 
 template <typename T, template <typename, int, int> class EpiT, typename P>
 int dispatch_nv(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, const P &p, int m,
-                double *partials, int *nparts, hipStream_t s) {
+                double *partials, int *nparts, hipStream_t s,
+                const LaunchEvents *ev = nullptr) {
   if (ld < m || ld > kMaxNev || m < 1) return SPHX_E_INVALID_ARG;
   const int row_bytes = ld * (int)sizeof(T);
 #define SPHX_NV(VB_, NV_)                                                                 \
   case NV_:                                                                               \
-    return dispatch_types<T, VB_, NV_, EpiT>(g, plan, X, ld, p, m, partials, nparts, s);
+    return dispatch_types<T, VB_, NV_, EpiT>(g, plan, X, ld, p, m, partials, nparts, s, ev);
   if (row_bytes % 16 == 0) {
     switch (row_bytes / 16) {
       SPHX_NV(16, 1) SPHX_NV(16, 2) SPHX_NV(16, 3) SPHX_NV(16, 4)
@@ -543,14 +553,14 @@ int vspmm_residual(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int 
 }
 template <typename T>
 int vspmm_cheb(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
-               EpiChebP<T> epi, hipStream_t s) {
-  return dispatch_nv<T, VCheb>(g, plan, X, ld, epi, m, nullptr, nullptr, s);
+               EpiChebP<T> epi, hipStream_t s, const LaunchEvents *ev) {
+  return dispatch_nv<T, VCheb>(g, plan, X, ld, epi, m, nullptr, nullptr, s, ev);
 }
 
 template <typename T>
 int vspmm_poly(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
-               EpiPolyP<T> epi, hipStream_t s) {
-  return dispatch_nv<T, VPoly>(g, plan, X, ld, epi, m, nullptr, nullptr, s);
+               EpiPolyP<T> epi, hipStream_t s, const LaunchEvents *ev) {
+  return dispatch_nv<T, VPoly>(g, plan, X, ld, epi, m, nullptr, nullptr, s, ev);
 }
 
 #define SPHX_VINST(T)                                                                       \
@@ -559,9 +569,9 @@ int vspmm_poly(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
   template int vspmm_residual<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,      \
                                  EpiResidualP<T>, double *, int *, hipStream_t);           \
   template int vspmm_cheb<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,          \
-                             EpiChebP<T>, hipStream_t);                                    \
+                             EpiChebP<T>, hipStream_t, const LaunchEvents *);              \
   template int vspmm_poly<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,          \
-                             EpiPolyP<T>, hipStream_t);
+                             EpiPolyP<T>, hipStream_t, const LaunchEvents *);
 SPHX_VINST(float)
 SPHX_VINST(double)
 #undef SPHX_VINST

@@ -295,6 +295,21 @@ def uniform_weights(count: int, seed: int, lo: float = 0.5, hi: float = 1.5,
     return (lo + (hi - lo) * rng.random(count)).astype(dtype)
 
 
+def perturb_weights(g: Graph, rel: float, seed: int, dtype=np.float64) -> Graph:
+    """The same graph with every edge weight scaled by a factor in
+    [1 - rel, 1 + rel) (unit weights taken as 1): a workload whose weights
+    drift between repartitionings.  The factor of an edge is a hash of its
+    end points and the seed, so both stored directions get the same value."""
+    iu = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.rowptr))
+    a = np.minimum(iu, g.col).astype(np.int64)
+    b = np.maximum(iu, g.col).astype(np.int64)
+    h = (a * 1000003 + b * 7919 + seed * 104729) % 1000
+    f = 1.0 + rel * (h / 500.0 - 1.0)
+    base = np.ones(g.col.size) if g.w is None else g.w.astype(np.float64)
+    return Graph(n=g.n, rowptr=g.rowptr, col=g.col, w=(base * f).astype(dtype),
+                 name=f"{g.name}+drift{rel:g}")
+
+
 def normal_block(n: int, m: int, seed: int, dtype=np.float64) -> np.ndarray:
     """n x m row-major block of i.i.d. N(0, 1) values (initial LOBPCG block)."""
     rng = np.random.default_rng(seed)

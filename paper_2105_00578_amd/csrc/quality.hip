@@ -13,36 +13,50 @@
 namespace sphx {
 namespace {
 
-// Each thread takes an equal slice of the CSR entries (any degree mix is
-// balanced); the row of its first entry is found by binary search in row_ptr.
+// Each block takes contiguous chunks of kCutChunk CSR entries; thread t
+// reads entries k0 + t + 256 q, so every load is coalesced.  The row of an
+// entry (the largest i with row_ptr[i] <= k) is found by binary search over
+// the chunk's rows, whose row_ptr values are staged in LDS when they fit.
 // Each thread accumulates an exact partial.
+constexpr int kCutChunk = 256 * 16;
+constexpr int kCutRows = 4096;
+
 template <typename IdxT, typename WT>
 __global__ __launch_bounds__(256) void k_cut(int64_t n, int64_t nnz, const IdxT *rp,
                                              const int32_t *col, const WT *w,
-                                             const int32_t *part, int e0, int64_t per_thread,
+                                             const int32_t *part, int e0,
                                              unsigned long long *out) {
+  __shared__ int64_t srp[kCutRows + 1];
+  __shared__ int64_t bounds[2];
   U128 acc{0, 0};
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t k0 = tid * per_thread;
-  const int64_t k1 = min(nnz, k0 + per_thread);
-  if (k0 < k1) {
-    // row i with rp[i] <= k0 < rp[i+1]
-    int64_t lo = 0, hi = n - 1;
+  const int tid = threadIdx.x;
+  auto row_of = [&](int64_t k, int64_t lo, int64_t hi, bool lds) {
+    // largest i in [lo, hi] with row_ptr[i] <= k (row_ptr[lo] <= k holds)
     while (lo < hi) {
-      int64_t mid = (lo + hi + 1) >> 1;
-      if ((int64_t)rp[mid] <= k0) lo = mid; else hi = mid - 1;
+      const int64_t mid = (lo + hi + 1) >> 1;
+      const int64_t v = lds ? srp[mid - bounds[0]] : (int64_t)rp[mid];
+      if (v <= k) lo = mid;
+      else hi = mid - 1;
     }
-    int64_t i = lo;
-    int64_t rend = rp[i + 1];
-    int pi = part[i];
-    for (int64_t k = k0; k < k1; ++k) {
-      while (k >= rend) {
-        ++i;
-        rend = rp[i + 1];
-        pi = part[i];
-      }
-      int64_t j = col[k];
-      if (j <= i || part[j] == pi) continue;
+    return lo;
+  };
+  for (int64_t c = blockIdx.x; c * kCutChunk < nnz; c += gridDim.x) {
+    const int64_t k0 = c * kCutChunk;
+    const int64_t k1 = min(nnz, k0 + kCutChunk);
+    if (tid == 0) {
+      bounds[0] = row_of(k0, 0, n - 1, false);
+      bounds[1] = row_of(k1 - 1, bounds[0], n - 1, false);
+    }
+    __syncthreads();
+    const int64_t r0 = bounds[0], r1 = bounds[1];
+    const bool lds = r1 - r0 + 1 <= kCutRows;
+    if (lds)
+      for (int64_t i = tid; i <= r1 - r0; i += 256) srp[i] = (int64_t)rp[r0 + i];
+    __syncthreads();
+    for (int64_t k = k0 + tid; k < k1; k += 256) {
+      const int64_t i = row_of(k, r0, r1, lds);
+      const int64_t j = col[k];
+      if (j <= i || part[j] == part[i]) continue;
       if constexpr (std::is_same_v<WT, Unit>) add128(acc, 1ull, 0ull);
       else {
         unsigned long long l, h;
@@ -50,12 +64,13 @@ __global__ __launch_bounds__(256) void k_cut(int64_t n, int64_t nnz, const IdxT 
         add128(acc, l, h);
       }
     }
+    __syncthreads();   // srp and bounds are rewritten for the next chunk
   }
   __shared__ unsigned long long slo[256], shi[256];
-  slo[threadIdx.x] = acc.lo;
-  shi[threadIdx.x] = acc.hi;
+  slo[tid] = acc.lo;
+  shi[tid] = acc.hi;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     U128 t{0, 0};
     for (int u = 0; u < (int)blockDim.x; ++u) add128(t, slo[u], shi[u]);
     out[2 * blockIdx.x] = t.lo;
@@ -131,15 +146,12 @@ int quality(sphx_graph *g, const int32_t *part, int K, double *cut, double *imba
   hipMemsetAsync(bad, 0, sizeof(int) * 4, s);
   hipLaunchKernelGGL(k_part_weights, dim3(grid_for(g->n, 256 * 16, 1024)), dim3(256), 0, s,
                      g->n, part, g->vwgt, K, pw, bad);
-  unsigned nb = kCutBlocks;
-  const int64_t per_thread = std::max<int64_t>(1, ceil_div(g->nnz, (int64_t)nb * 256));
-  nb = (unsigned)std::max<int64_t>(1, ceil_div(ceil_div(g->nnz, per_thread), 256));
+  const unsigned nb = grid_for(g->nnz, kCutChunk, kCutBlocks);
   auto go = [&](auto it, auto wt) {
     using IdxT = decltype(it);
     using WT = decltype(wt);
     hipLaunchKernelGGL((k_cut<IdxT, WT>), dim3(nb), dim3(256), 0, s, g->n, g->nnz,
-                       (const IdxT *)g->rowptr, g->col, (const WT *)g->w, part, e0,
-                       per_thread, cp);
+                       (const IdxT *)g->rowptr, g->col, (const WT *)g->w, part, e0, cp);
   };
   if (g->rp64) {
     if (g->wdt == SPHX_UNIT) go(int64_t{}, Unit{});

@@ -110,48 +110,76 @@ __global__ __launch_bounds__(256) void k_gain_thread(int64_t n, const IdxT *__re
 }
 
 // Step 1 for the listed rows (kThreadDeg < degree <= kRefineMaxDeg): one
-// block per row, the row's neighbour parts in LDS.
+// block per row, the row's neighbour parts in LDS.  With unit weights and at
+// most kLdsParts parts, conn(v, p) is counted in an LDS table indexed by part
+// (integer counts: the order of the increments does not matter); otherwise
+// each distinct part's connection is summed over the row (first occurrence
+// of the part owns the sum).
+constexpr int kLdsParts = 8192;
+
 template <typename IdxT, typename WT>
 __global__ __launch_bounds__(256) void k_gain_block(const int32_t *__restrict__ rows,
                                                     const int32_t *__restrict__ nrows,
                                                     const IdxT *__restrict__ rp,
                                                     const int32_t *__restrict__ col,
                                                     const WT *__restrict__ w, int e0,
-                                                    const int32_t *__restrict__ part,
+                                                    const int32_t *__restrict__ part, int K,
                                                     int32_t *tgt, S *gain) {
   __shared__ int32_t sp[kRefineMaxDeg];
+  __shared__ int32_t cnt[kLdsParts];
   __shared__ S rc[4], ra[4];
   __shared__ int rt[4];
+  constexpr bool kUnit = std::is_same_v<WT, Unit>;
+  const bool table = kUnit && K <= kLdsParts;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (table) {
+    for (int k = tid; k < K; k += 256) cnt[k] = 0;
+    __syncthreads();
+  }
   const int nr = *nrows;
   for (int r = blockIdx.x; r < nr; r += gridDim.x) {
     const int64_t v = rows[r];
     const int64_t lo = rp[v];
     const int d = (int)((int64_t)rp[v + 1] - lo);   // kThreadDeg < d <= kRefineMaxDeg
     const int a = part[v];
-    for (int j = tid; j < d; j += 256) sp[j] = part[col[lo + j]];
+    for (int j = tid; j < d; j += 256) {
+      const int p = part[col[lo + j]];
+      sp[j] = p;
+      if (table) atomicAdd(&cnt[p], 1);
+    }
     __syncthreads();
     S ca = 0, best = 0;
     int t = -1;
-    for (int j = tid; j < d; j += 256) {
-      const int p = sp[j];
-      if (p == a) {
-        ca += wfix(w, lo + j, e0);
-        continue;
-      }
-      bool first = true;
-      for (int q = 0; q < j; ++q)
-        if (sp[q] == p) {
-          first = false;
-          break;
+    if (table) {
+      if (tid == 0) ca = cnt[a];
+      for (int j = tid; j < d; j += 256) {
+        const int p = sp[j];
+        if (p != a && better((S)cnt[p], p, best, t)) {
+          best = cnt[p];
+          t = p;
         }
-      if (!first) continue;
-      S c = 0;
-      for (int q = j; q < d; ++q)
-        if (sp[q] == p) c += wfix(w, lo + q, e0);
-      if (better(c, p, best, t)) {
-        best = c;
-        t = p;
+      }
+    } else {
+      for (int j = tid; j < d; j += 256) {
+        const int p = sp[j];
+        if (p == a) {
+          ca += wfix(w, lo + j, e0);
+          continue;
+        }
+        bool first = true;
+        for (int q = 0; q < j; ++q)
+          if (sp[q] == p) {
+            first = false;
+            break;
+          }
+        if (!first) continue;
+        S c = 0;
+        for (int q = j; q < d; ++q)
+          if (sp[q] == p) c += wfix(w, lo + q, e0);
+        if (better(c, p, best, t)) {
+          best = c;
+          t = p;
+        }
       }
     }
     for (int off = 32; off >= 1; off >>= 1) {
@@ -169,6 +197,8 @@ __global__ __launch_bounds__(256) void k_gain_block(const int32_t *__restrict__ 
       ra[wv] = ca;
     }
     __syncthreads();
+    if (table)   // clear the counts of this row (every read above is done)
+      for (int j = tid; j < d; j += 256) cnt[sp[j]] = 0;
     if (tid == 0) {
       S B = rc[0], A = ra[0];
       int T = rt[0];
@@ -190,6 +220,29 @@ __global__ __launch_bounds__(256) void k_gain_block(const int32_t *__restrict__ 
 // Step 2: a candidate stays a mover when its gain, with every higher-ranked
 // candidate neighbour at its target, is positive.
 template <typename IdxT, typename WT>
+__device__ __forceinline__ S moved_gain(int64_t v, int64_t k0, int64_t k1, int64_t step,
+                                        const int32_t *__restrict__ col,
+                                        const WT *__restrict__ w, int e0,
+                                        const int32_t *__restrict__ part,
+                                        const int32_t *__restrict__ tgt,
+                                        const S *__restrict__ gain, int a, int t, S gv) {
+  S g2 = 0;
+  for (int64_t k = k0; k < k1; k += step) {
+    const int64_t u = col[k];
+    int pu = part[u];
+    const int tu = tgt[u];
+    if (tu >= 0) {
+      const S gu = gain[u];
+      if (gu > gv || (gu == gv && u < v)) pu = tu;
+    }
+    if (pu == t) g2 += wfix(w, k, e0);
+    else if (pu == a) g2 -= wfix(w, k, e0);
+  }
+  return g2;
+}
+
+// rows of degree <= kThreadDeg (and the rows that never move): one thread each
+template <typename IdxT, typename WT>
 __global__ __launch_bounds__(256) void k_movers(int64_t n, const IdxT *__restrict__ rp,
                                                 const int32_t *__restrict__ col,
                                                 const WT *__restrict__ w, int e0,
@@ -198,26 +251,44 @@ __global__ __launch_bounds__(256) void k_movers(int64_t n, const IdxT *__restric
                                                 const S *__restrict__ gain, uint8_t *mv) {
   for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * 256) {
+    const int64_t k0 = rp[v], k1 = rp[v + 1];
+    const int64_t d = k1 - k0;
+    if (d > kThreadDeg && d <= kRefineMaxDeg) continue;   // k_movers_wave
     const int t = tgt[v];
     uint8_t f = 0;
-    if (t >= 0) {
-      const int a = part[v];
-      const S gv = gain[v];
-      S g2 = 0;
-      for (int64_t k = rp[v]; k < (int64_t)rp[v + 1]; ++k) {
-        const int64_t u = col[k];
-        int pu = part[u];
-        const int tu = tgt[u];
-        if (tu >= 0) {
-          const S gu = gain[u];
-          if (gu > gv || (gu == gv && u < v)) pu = tu;
-        }
-        if (pu == t) g2 += wfix(w, k, e0);
-        else if (pu == a) g2 -= wfix(w, k, e0);
-      }
-      f = g2 > 0 ? 1 : 0;
-    }
+    if (t >= 0)
+      f = moved_gain<IdxT, WT>(v, k0, k1, 1, col, w, e0, part, tgt, gain, part[v], t,
+                               gain[v]) > 0
+              ? 1
+              : 0;
     mv[v] = f;
+  }
+}
+
+// the listed rows (kThreadDeg < degree <= kRefineMaxDeg): one wave each
+template <typename IdxT, typename WT>
+__global__ __launch_bounds__(256) void k_movers_wave(const int32_t *__restrict__ rows,
+                                                     const int32_t *__restrict__ nrows,
+                                                     const IdxT *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     const WT *__restrict__ w, int e0,
+                                                     const int32_t *__restrict__ part,
+                                                     const int32_t *__restrict__ tgt,
+                                                     const S *__restrict__ gain, uint8_t *mv) {
+  const int lane = threadIdx.x & 63;
+  const int nr = *nrows;
+  for (int r = (blockIdx.x * 256 + threadIdx.x) >> 6; r < nr; r += (gridDim.x * 256) >> 6) {
+    const int64_t v = rows[r];
+    const int t = tgt[v];
+    if (t < 0) {                       // wave-uniform
+      if (lane == 0) mv[v] = 0;
+      continue;
+    }
+    const int64_t k0 = rp[v], k1 = rp[v + 1];
+    S g2 = moved_gain<IdxT, WT>(v, k0 + lane, k1, 64, col, w, e0, part, tgt, gain, part[v], t,
+                                gain[v]);
+    for (int off = 32; off >= 1; off >>= 1) g2 += shfl_xor_s(g2, off);
+    if (lane == 0) mv[v] = g2 > 0 ? 1 : 0;
   }
 }
 
@@ -283,23 +354,30 @@ __global__ void k_zero_u64(unsigned long long *x, int64_t cnt) {
     x[i] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_part_weight(int64_t n, const int32_t *__restrict__ part,
-                                                     const int32_t *__restrict__ vwgt,
-                                                     unsigned long long *W) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * 256)
-    atomicAdd(&W[part[i]], (unsigned long long)(vwgt ? vwgt[i] : 1));
-}
-
+// total weight of the movers into each part; up to kLdsParts parts are
+// summed in LDS first (integer sums: the order does not matter)
 __global__ __launch_bounds__(256) void k_arrivals(const int32_t *__restrict__ list,
                                                   const int32_t *__restrict__ count,
                                                   const int32_t *__restrict__ tgt,
-                                                  const int32_t *__restrict__ vwgt,
+                                                  const int32_t *__restrict__ vwgt, int K,
                                                   unsigned long long *arr) {
+  __shared__ unsigned long long hst[kLdsParts];
+  const bool lds = K <= kLdsParts;
+  if (lds) {
+    for (int k = threadIdx.x; k < K; k += 256) hst[k] = 0;
+    __syncthreads();
+  }
   const int M = *count;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < M; i += gridDim.x * 256) {
     const int v = list[i];
-    atomicAdd(&arr[tgt[v]], (unsigned long long)(vwgt ? vwgt[v] : 1));
+    const unsigned long long c = (unsigned long long)(vwgt ? vwgt[v] : 1);
+    if (lds) atomicAdd(&hst[tgt[v]], c);
+    else atomicAdd(&arr[tgt[v]], c);
+  }
+  if (lds) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += 256)
+      if (hst[k]) atomicAdd(&arr[k], hst[k]);
   }
 }
 
@@ -324,56 +402,125 @@ __global__ __launch_bounds__(256) void k_accept_all(const int32_t *__restrict__ 
   if (c) atomicAdd(moved, c);
 }
 
-// Parts whose arrivals exceed the capacity: one block per part takes its
-// movers in list (= vertex) order and accepts the prefix that fits.
-__global__ __launch_bounds__(256) void k_accept_prefix(const int32_t *__restrict__ list,
-                                                       const int32_t *__restrict__ count,
-                                                       const int32_t *__restrict__ tgt,
-                                                       const int32_t *__restrict__ vwgt, int K,
-                                                       const unsigned long long *__restrict__ W,
-                                                       const unsigned long long *__restrict__ arr,
-                                                       unsigned long long cap, int32_t *nxt,
-                                                       unsigned long long *moved) {
+// Parts whose arrivals exceed the capacity ("overflowing": some but not all
+// of their movers fit) accept the prefix of their movers, in list (= vertex)
+// order, that fits.  The list is cut into kPrefChunks chunks: per
+// (overflowing part, chunk) the movers' weight is summed, scanned over the
+// chunks, and each chunk then accepts its movers with a block scan from that
+// offset.
+constexpr int kPrefChunks = 256;
+constexpr int kMaxOver = 16384;   // overflowing parts handled per launch batch
+
+__global__ void k_over_flags(int K, const unsigned long long *__restrict__ W,
+                             const unsigned long long *__restrict__ arr, unsigned long long cap,
+                             uint8_t *of) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < K; p += gridDim.x * blockDim.x)
+    of[p] = (W[p] + arr[p] > cap && W[p] < cap) ? 1 : 0;
+}
+
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x,
+                                                            unsigned long long *ws) {
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = x;
+  __syncthreads();
+  return ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(256) void k_over_sums(const int32_t *__restrict__ list,
+                                                   const int32_t *__restrict__ count,
+                                                   const int32_t *__restrict__ tgt,
+                                                   const int32_t *__restrict__ vwgt,
+                                                   const int32_t *__restrict__ olist,
+                                                   const int32_t *__restrict__ ocount, int o0,
+                                                   unsigned long long *sums) {
+  __shared__ unsigned long long ws[4];
+  const int M = *count, O = min(*ocount, o0 + kMaxOver);
+  const int per = (M + kPrefChunks - 1) / kPrefChunks;
+  const int i0 = blockIdx.x * per, i1 = min(M, i0 + per);
+  for (int o = o0 + blockIdx.y; o < O; o += gridDim.y) {
+    const int p = olist[o];
+    unsigned long long acc = 0;
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+      const int v = list[i];
+      if (tgt[v] == p) acc += (unsigned long long)(vwgt ? vwgt[v] : 1);
+    }
+    acc = block_sum_u64(acc, ws);
+    if (threadIdx.x == 0) sums[(int64_t)(o - o0) * kPrefChunks + blockIdx.x] = acc;
+  }
+}
+
+// exclusive scan of each overflowing part's chunk sums
+__global__ __launch_bounds__(kPrefChunks) void k_over_scan(const int32_t *__restrict__ ocount,
+                                                           int o0, unsigned long long *sums) {
+  __shared__ unsigned long long sh[kPrefChunks];
+  const int O = min(*ocount, o0 + kMaxOver);
+  const int t = threadIdx.x;
+  for (int o = o0 + blockIdx.x; o < O; o += gridDim.x) {
+    unsigned long long *row = sums + (int64_t)(o - o0) * kPrefChunks;
+    sh[t] = row[t];
+    __syncthreads();
+    for (int off = 1; off < kPrefChunks; off <<= 1) {
+      const unsigned long long x = t >= off ? sh[t - off] : 0ull;
+      __syncthreads();
+      sh[t] += x;
+      __syncthreads();
+    }
+    row[t] = t ? sh[t - 1] : 0ull;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_over_accept(const int32_t *__restrict__ list,
+                                                     const int32_t *__restrict__ count,
+                                                     const int32_t *__restrict__ tgt,
+                                                     const int32_t *__restrict__ vwgt,
+                                                     const int32_t *__restrict__ olist,
+                                                     const int32_t *__restrict__ ocount, int o0,
+                                                     const unsigned long long *__restrict__ W,
+                                                     const unsigned long long *__restrict__ sums,
+                                                     unsigned long long cap, int32_t *nxt,
+                                                     unsigned long long *moved) {
   __shared__ unsigned long long ws[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int M = *count;
-  for (int p = blockIdx.x; p < K; p += gridDim.x) {
-    const unsigned long long Wp = W[p];
-    if (Wp + arr[p] <= cap || Wp >= cap) {
-      // all fit (k_accept_all took them), or none can
-      continue;
-    }
-    unsigned long long run = 0, acc = 0;
-    for (int b = 0; b < M; b += 256) {
+  const int M = *count, O = min(*ocount, o0 + kMaxOver);
+  const int per = (M + kPrefChunks - 1) / kPrefChunks;
+  const int i0 = blockIdx.x * per, i1 = min(M, i0 + per);
+  unsigned long long acc = 0;
+  for (int o = o0 + blockIdx.y; o < O; o += gridDim.y) {
+    const int p = olist[o];
+    const unsigned long long base = W[p] + sums[(int64_t)(o - o0) * kPrefChunks + blockIdx.x];
+    if (base >= cap) continue;   // block-uniform: no mover of this chunk fits
+    unsigned long long run = 0;
+    for (int b = i0; b < i1; b += 256) {
       const int i = b + tid;
       int v = -1;
       unsigned long long x = 0;
-      if (i < M) {
+      if (i < i1) {
         v = list[i];
         if (tgt[v] == p) x = (unsigned long long)(vwgt ? vwgt[v] : 1);
       }
-      // inclusive scan over the block
-      unsigned long long s = x;
+      unsigned long long sc = x;   // inclusive scan over the block
       for (int off = 1; off < 64; off <<= 1) {
-        const unsigned long long y = __shfl_up(s, off);
-        if (lane >= off) s += y;
+        const unsigned long long y = __shfl_up(sc, off);
+        if (lane >= off) sc += y;
       }
-      if (lane == 63) ws[wv] = s;
+      if (lane == 63) ws[wv] = sc;
       __syncthreads();
       unsigned long long pre = 0;
       for (int q = 0; q < wv; ++q) pre += ws[q];
       const unsigned long long tot = ws[0] + ws[1] + ws[2] + ws[3];
-      if (x && Wp + run + pre + s <= cap) {
+      if (x && base + run + pre + sc <= cap) {
         nxt[v] = p;
         ++acc;
       }
       run += tot;
       __syncthreads();
-      if (Wp + run > cap) break;   // block-uniform: every later mover is rejected
+      if (base + run > cap) break;   // block-uniform: every later mover is rejected
     }
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0 && acc) atomicAdd(moved, acc);
   }
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0 && acc) atomicAdd(moved, acc);
 }
 
 __global__ void k_copy_i32(const int32_t *__restrict__ a, int32_t *b, int64_t n) {
@@ -392,6 +539,9 @@ size_t refine_scratch_bytes(int64_t n, int K) {
   b += align_up(sizeof(int32_t) * (kScanBlocks + 1), 256) * 2;       // block counts
   b += align_up(sizeof(unsigned long long) * (size_t)K, 256) * 2;    // W, arrivals
   b += align_up(sizeof(unsigned long long) * 4, 256);                // counters
+  b += align_up((size_t)K, 256) + align_up(sizeof(int32_t) * (size_t)K, 256);   // overflow
+  b += align_up(sizeof(int32_t) * (kScanBlocks + 1), 256);
+  b += align_up(sizeof(unsigned long long) * (size_t)std::min(K, kMaxOver) * kPrefChunks, 256);
   b += quality_scratch_bytes(K) + 256;
   return b;
 }
@@ -414,6 +564,11 @@ int refine(sphx_graph *g, int32_t *part, int K, double eps, int max_passes, doub
   unsigned long long *W = a.take<unsigned long long>(K);
   unsigned long long *arr = a.take<unsigned long long>(K);
   unsigned long long *ctr = a.take<unsigned long long>(4);
+  uint8_t *oflag = a.take<uint8_t>(K);
+  int32_t *olist = a.take<int32_t>(K);
+  int32_t *cnt_of = a.take<int32_t>(kScanBlocks + 1);
+  unsigned long long *osums =
+      a.take<unsigned long long>((size_t)std::min(K, kMaxOver) * kPrefChunks);
   char *qscratch = a.take<char>(quality_scratch_bytes(K));
   int e0 = 0;
   if (g->wdt == SPHX_F32) e0 = fixed_exponent<float>(g->wmin);
@@ -421,6 +576,7 @@ int refine(sphx_graph *g, int32_t *part, int K, double eps, int max_passes, doub
 
   // current partition: its exact cut, part weights (and the range check)
   std::vector<int64_t> pw(K);
+  std::vector<unsigned long long> hW(K);
   unsigned __int128 cut_cur = 0;
   double c_d = 0.0, imb = 1.0;
   SPHX_TRY(quality(g, part, K, &c_d, &imb, pw.data(), qscratch, pinned, s, err, &cut_cur));
@@ -450,12 +606,16 @@ int refine(sphx_graph *g, int32_t *part, int K, double eps, int max_passes, doub
       hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(kScanBlocks), 0, s, cnt_rows);
       hipLaunchKernelGGL(k_flag_scatter, dim3(kScanBlocks), dim3(256), 0, s, n,
                          (const uint8_t *)big, (const int32_t *)cnt_rows, rows);
-      hipLaunchKernelGGL((k_gain_block<IdxT, WT>), dim3(4096), dim3(256), 0, s,
-                         (const int32_t *)rows, (const int32_t *)(cnt_rows + kScanBlocks), rp,
-                         g->col, w, e0, (const int32_t *)cur, tgt, gain);
+      const int32_t *nbig = cnt_rows + kScanBlocks;
+      hipLaunchKernelGGL((k_gain_block<IdxT, WT>), dim3(2048), dim3(256), 0, s,
+                         (const int32_t *)rows, nbig, rp, g->col, w, e0, (const int32_t *)cur, K,
+                         tgt, gain);
       // 2. conflicts
       hipLaunchKernelGGL((k_movers<IdxT, WT>), dim3(gv), dim3(256), 0, s, n, rp, g->col, w, e0,
                          (const int32_t *)cur, (const int32_t *)tgt, (const S *)gain, mv);
+      hipLaunchKernelGGL((k_movers_wave<IdxT, WT>), dim3(2048), dim3(256), 0, s,
+                         (const int32_t *)rows, nbig, rp, g->col, w, e0, (const int32_t *)cur,
+                         (const int32_t *)tgt, (const S *)gain, mv);
       hipLaunchKernelGGL(k_flag_count, dim3(kScanBlocks), dim3(256), 0, s, n,
                          (const uint8_t *)mv, cnt_mv);
       hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(kScanBlocks), 0, s, cnt_mv);
@@ -463,23 +623,41 @@ int refine(sphx_graph *g, int32_t *part, int K, double eps, int max_passes, doub
                          (const uint8_t *)mv, (const int32_t *)cnt_mv, list);
       // 3. balance, 4. moves (into a copy of the current partition)
       const int32_t *M = cnt_mv + kScanBlocks;
-      hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(K, 256, 1024)), dim3(256), 0, s, W,
-                         (int64_t)K);
+      // part weights of the current partition (from its quality pass)
+      for (int k = 0; k < K; ++k) hW[k] = (unsigned long long)pw[k];
+      SPHX_HIP(g->h, hipMemcpyAsync(W, hW.data(), sizeof(unsigned long long) * K,
+                                    hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(K, 256, 1024)), dim3(256), 0, s, arr,
                          (int64_t)K);
       hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr, (int64_t)4);
-      hipLaunchKernelGGL(k_part_weight, dim3(gv), dim3(256), 0, s, n, (const int32_t *)cur,
-                         g->vwgt, W);
-      hipLaunchKernelGGL(k_arrivals, dim3(gv), dim3(256), 0, s, (const int32_t *)list, M,
-                         (const int32_t *)tgt, g->vwgt, arr);
+      hipLaunchKernelGGL(k_arrivals, dim3(grid_for(n, 256 * 16, 1024)), dim3(256), 0, s,
+                         (const int32_t *)list, M, (const int32_t *)tgt, g->vwgt, K, arr);
       hipLaunchKernelGGL(k_copy_i32, dim3(gv), dim3(256), 0, s, (const int32_t *)cur, alt, n);
       hipLaunchKernelGGL(k_accept_all, dim3(gv), dim3(256), 0, s, (const int32_t *)list, M,
                          (const int32_t *)tgt, (const unsigned long long *)W,
                          (const unsigned long long *)arr, cap, alt, ctr);
-      hipLaunchKernelGGL(k_accept_prefix, dim3((unsigned)std::min(K, 4096)), dim3(256), 0, s,
-                         (const int32_t *)list, M, (const int32_t *)tgt, g->vwgt, K,
+      // overflowing parts: prefix acceptance in vertex order
+      hipLaunchKernelGGL(k_over_flags, dim3(grid_for(K, 256, 1024)), dim3(256), 0, s, K,
                          (const unsigned long long *)W, (const unsigned long long *)arr, cap,
-                         alt, ctr);
+                         oflag);
+      hipLaunchKernelGGL(k_flag_count, dim3(kScanBlocks), dim3(256), 0, s, (int64_t)K,
+                         (const uint8_t *)oflag, cnt_of);
+      hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(kScanBlocks), 0, s, cnt_of);
+      hipLaunchKernelGGL(k_flag_scatter, dim3(kScanBlocks), dim3(256), 0, s, (int64_t)K,
+                         (const uint8_t *)oflag, (const int32_t *)cnt_of, olist);
+      const int32_t *O = cnt_of + kScanBlocks;
+      for (int o0 = 0; o0 < K; o0 += kMaxOver) {
+        const unsigned gy = (unsigned)std::min(std::min(K - o0, kMaxOver), 64);
+        hipLaunchKernelGGL(k_over_sums, dim3(kPrefChunks, gy), dim3(256), 0, s,
+                           (const int32_t *)list, M, (const int32_t *)tgt, g->vwgt,
+                           (const int32_t *)olist, O, o0, osums);
+        hipLaunchKernelGGL(k_over_scan, dim3(std::min(std::min(K - o0, kMaxOver), 1024)),
+                           dim3(kPrefChunks), 0, s, O, o0, osums);
+        hipLaunchKernelGGL(k_over_accept, dim3(kPrefChunks, gy), dim3(256), 0, s,
+                           (const int32_t *)list, M, (const int32_t *)tgt, g->vwgt,
+                           (const int32_t *)olist, O, o0, (const unsigned long long *)W,
+                           (const unsigned long long *)osums, cap, alt, ctr);
+      }
       if (hipGetLastError() != hipSuccess) {
         *err = "refinement kernel launch failed";
         return SPHX_E_HIP;

@@ -163,17 +163,6 @@ def test_refine_full_size_properties(handle, graph, K):
 
 # ---- warm-start repartitioning
 
-def _perturbed(g, seed, rel):
-    iu = np.repeat(np.arange(g.n), np.diff(g.rowptr))
-    base = np.ones(g.col.size) if g.w is None else g.w.astype(np.float64)
-    # symmetric perturbation: the factor of an edge depends on its end points
-    a = np.minimum(iu, g.col).astype(np.int64)
-    b = np.maximum(iu, g.col).astype(np.int64)
-    h = (a * 1000003 + b * 7919 + seed) % 1000
-    f = 1.0 + rel * (h / 500.0 - 1.0)
-    return graphgen.Graph(n=g.n, rowptr=g.rowptr, col=g.col, w=base * f, name=g.name)
-
-
 @pytest.mark.parametrize("problem", [sx.COMBINATORIAL, sx.GENERALIZED, sx.NORMALIZED])
 def test_warm_start_repartition(handle, problem):
     """Weights change by up to 1 %: the solve started from the previous
@@ -182,7 +171,7 @@ def test_warm_start_repartition(handle, problem):
     n0, (u, v) = graphgen.grid2d_9pt(24, 20)
     g0 = graphgen.csr_from_edges(n0, u, v, graphgen.uniform_weights(u.size, 3,
                                                                      dtype=np.float64))
-    g1 = _perturbed(g0, 4, 0.01)
+    g1 = graphgen.perturb_weights(g0, 0.01, 4)
     K = 8
     nev = sx.num_eigenvectors(K)
     opts = sx.Options(problem=problem, precond=sx.PRECOND_JACOBI, tol=1e-8,

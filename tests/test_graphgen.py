@@ -81,3 +81,21 @@ def test_brick100_matches_the_paper_edge_count():
     g = graphgen.config_graph("brick100", scale_down=1)
     assert g.n == 1_000_000
     assert int(g.rowptr[-1]) + g.n == 26_463_592
+
+
+def test_perturb_weights_symmetric_and_bounded():
+    n, (u, v) = graphgen.grid2d_9pt(20, 15)
+    g = graphgen.csr_from_edges(n, u, v, graphgen.uniform_weights(u.size, 2, dtype=np.float64))
+    h = graphgen.perturb_weights(g, 0.01, 3)
+    iu = np.repeat(np.arange(n), np.diff(g.rowptr))
+    f = h.w / g.w
+    assert np.all((f >= 0.99 - 1e-15) & (f < 1.01))
+    # the entry (i, j) and its mirror (j, i) carry the same weight
+    key = iu * n + g.col
+    mirror = g.col * n + iu
+    order = np.argsort(key)
+    pos = order[np.searchsorted(key[order], mirror)]
+    assert np.array_equal(h.w, h.w[pos])
+    assert np.unique(np.round(f, 6)).size > 100
+    u1 = graphgen.perturb_weights(graphgen.csr_from_edges(n, u, v), 0.05, 1, dtype=np.float32)
+    assert u1.w.dtype == np.float32 and abs(u1.w.astype(np.float64) - 1).max() <= 0.05 + 1e-7

@@ -20,7 +20,9 @@ __host__ __device__ constexpr int bin_group(int c) {
   return c == 0 ? 1 : (c == 1 ? 4 : (c == 2 ? 16 : 64));
 }
 // Graphs whose rows all have at most this many neighbours are not binned:
-// every row in natural order, `group` lanes per row.
+// every row in natural order, `group` lanes per row (for rows of more than 12
+// neighbours the product picks 1, 2 or 4 lanes from the gathered row width
+// and the weight stream).
 constexpr int kUnbinnedMaxDeg = 48;
 
 struct SpmmPlan {

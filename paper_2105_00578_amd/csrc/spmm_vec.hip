@@ -306,7 +306,7 @@ __device__ __forceinline__ void group_sum(typename Vec<T, VB>::type (&acc)[NV]) 
     }
 }
 
-// G lanes per row (G = 4, 16 or 64): the lanes of a group take every G-th
+// G lanes per row (G = 2, 4, 16 or 64): the lanes of a group take every G-th
 // neighbour of the row, so a group reads a contiguous run of the column
 // indices; the group's partial sums are combined by a butterfly in a fixed
 // order and the group's first lane runs the epilogue.  rows = null: natural
@@ -439,7 +439,10 @@ void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X
   };
   auto grouped = [&](int G, const int32_t *rows, int64_t nr, int64_t maxb) {
     unsigned gb = grid_for(nr, 256 / G, maxb);
-    if (G == 4)
+    if (G == 2)
+      hipExtLaunchKernelGGL((k_vgroup<T, VB, NV, 2, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
+                            e0, e1, 0, A, rows, nr, X, ld, epi, partials, used, m);
+    else if (G == 4)
       hipExtLaunchKernelGGL((k_vgroup<T, VB, NV, 4, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
                             e0, e1, 0, A, rows, nr, X, ld, epi, partials, used, m);
     else if (G == 16)
@@ -451,8 +454,13 @@ void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X
     used += (int)gb;
   };
   if (!plan.binned) {
-    if (plan.group == 1) short_rows(nullptr, n, kMaxShortBlocks);
-    else grouped(plan.group, nullptr, n, kGroupBlocks);
+    // rows of 13..48 neighbours: wide gathered rows (>= 32 bytes) amortise a
+    // lane's serial walk over the row (one lane per row for unit weights, two
+    // when a weight stream rides along); narrow rows take four lanes
+    int G = plan.group;
+    if (G > 1 && VB * NV >= 32) G = std::is_same_v<WT, Unit> ? 1 : 2;
+    if (G == 1) short_rows(nullptr, n, kMaxShortBlocks);
+    else grouped(G, nullptr, n, kGroupBlocks);
   } else {
     for (int c = 0; c < kNumBins; ++c) {
       if (plan.nrows[c] == 0) continue;

@@ -12,10 +12,17 @@ Metric: Laplacian SpMM HBM GB/s and time to the K-way eigenvectors in mixed
 precision (FP32 SpMM / preconditioner / updates, FP64 Gram and
 Rayleigh-Ritz) vs all-FP64 at the same residual tolerance.  `value` is the
 GB/s of the dominant kernel (the fused Chebyshev-step Laplacian product):
-algorithmic bytes of all its launches in the timed steps divided by their
-summed durations, measured with HIP events on the library's stream.
+algorithmic bytes of all its launches in the timed steps (over the int32
+CSR the caller passes) divided by their summed durations, measured with
+events that each launch's dispatch stamps on the library's stream.  On this
+grid the kernels read the column indices as int16 offsets from the row
+(`roofline.col_index_bytes_read`), so the bytes they move are fewer than the
+algorithmic count; `roofline.traffic` gives the measured bytes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --workload NAME      (another configuration)
+       python bench.py --repartition        (also: greedy refinement and a
+                                      warm-started repartition)
        python bench.py --only-mixed --steps 1 --warmup 0 --no-cpu-baseline
                                       (one mixed partition, for counter runs)
        python bench.py --copy-probe BYTES   (one plain device copy of BYTES,
@@ -220,6 +227,7 @@ def run(args):
             cheb_avg_us=msp / max(1, sum(s.precond_calls for s in sts)) * 1e3,
             cheb_calls=sum(s.precond_calls for s in sts),
             avg_active_cols=sum(s.precond_cols for s in sts) / max(1, sum(s.iterations for s in sts)),
+            col_index_bytes=st.col_index_bytes,
             spmm_gbs=gbs / (mss * 1e-3) if mss > 0 else 0.0,
             spmm_calls=sum(s.spmm_calls for s in sts),
             phases_ms={k: round(v / 1.0, 3) for k, v in st.phases_ms.items()},
@@ -265,6 +273,9 @@ def run(args):
             "avg_launch_us": round(mx["cheb_avg_us"], 3) if cheb else None,
             "launches": mx["cheb_calls"] if cheb else mx["spmm_calls"],
             "avg_active_cols": round(mx["avg_active_cols"], 3),
+            # the kernel reads this many bytes per column index (2: int16
+            # offsets from the row); `achieved` counts 4, the int32 CSR input
+            "col_index_bytes_read": mx["col_index_bytes"],
         },
         "time_to_eigvecs_ms": {"mixed": round(mx["time_to_eigvecs_ms"], 3),
                                "fp64": round(f64["time_to_eigvecs_ms"], 3)},

@@ -130,6 +130,13 @@ typedef struct sphx_stats {
                                     once (gathered rows counted once)         */
     int64_t precond_cols; /* sum over preconditioner applies of the number of
                              active (unconverged) columns they served         */
+    int32_t col_index_bytes; /* bytes per column index the vector products
+                                read: 2 when the graph (unit weights, 32-bit
+                                row pointers, at most 48 neighbours per row,
+                                every neighbour within 32767 rows) is stored
+                                as int16 offsets from the row, else 4.  The
+                                algorithmic GB above count 4 (the int32 CSR
+                                the caller passed).                           */
 } sphx_stats;
 
 /* ---------------------------------------------------------------- basics */

@@ -40,7 +40,8 @@ class _Stats(C.Structure):
                 ("ms_update", C.c_double), ("ms_split", C.c_double),
                 ("ms_quality", C.c_double), ("spmm_calls", C.c_int64),
                 ("precond_calls", C.c_int64), ("gb_spmm", C.c_double),
-                ("gb_precond", C.c_double), ("precond_cols", C.c_int64)]
+                ("gb_precond", C.c_double), ("precond_cols", C.c_int64),
+                ("col_index_bytes", C.c_int32)]
 
 
 def _load():
@@ -167,6 +168,7 @@ class Stats:
     gb_spmm: float
     gb_precond: float
     precond_cols: int
+    col_index_bytes: int
 
 
 def _stats(s: _Stats, nev: int) -> Stats:
@@ -174,7 +176,8 @@ def _stats(s: _Stats, nev: int) -> Stats:
               ("setup", "spmm", "precond", "gram", "rr", "update", "split", "quality")}
     return Stats(s.iterations, s.converged, s.restarts, s.graph_regular, s.max_degree,
                  s.avg_degree, list(s.rho[: min(nev, 32)]), s.ms_total, phases,
-                 s.spmm_calls, s.precond_calls, s.gb_spmm, s.gb_precond, s.precond_cols)
+                 s.spmm_calls, s.precond_calls, s.gb_spmm, s.gb_precond, s.precond_cols,
+                 s.col_index_bytes)
 
 
 def _torch():

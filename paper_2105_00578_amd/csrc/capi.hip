@@ -217,6 +217,8 @@ ChebCoef cheb_coef(int degree, double lo, double hi) {
 // Algorithmic bytes of one Laplacian product over G columns of s-byte
 // values: index arrays once, `vec_passes` block passes (the gathered source
 // counted once), `row_doubles` FP64 per-row values.
+// Algorithmic bytes of one product over the caller's int32 CSR (int16 column
+// offsets, when the plan has them, are read in half the index bytes).
 double spmm_bytes(const sphx_graph *g, const SpmmPlan &plan, int G, int s, int vec_passes,
                   int row_doubles) {
   double b = (g->rp64 ? 8.0 : 4.0) * double(g->n + 1) + 4.0 * double(g->nnz);
@@ -638,6 +640,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     stats->spmm_calls = calls;
     stats->precond_calls = pcalls;
     stats->precond_cols = pcols;
+    stats->col_index_bytes = w.plan.dcol ? 2 : 4;
     stats->ms_total = tall.stop(s);
   } else {
     SPHX_HIP(h, hipStreamSynchronize(s));

@@ -28,6 +28,9 @@ constexpr int kUnbinnedMaxDeg = 48;
 struct SpmmPlan {
   bool binned = false;          // false: natural row order, `group` lanes per row
   int group = 1;
+  // unbinned unit-weight graphs with 32-bit row pointers whose neighbours all
+  // lie within 32767 rows: column offsets from the row, 2 bytes per entry
+  const int16_t *dcol = nullptr;
   const int32_t *rows[kNumBins] = {};    // row lists of the classes (binned)
   int64_t nrows[kNumBins] = {};
   const int32_t *hub_rows = nullptr;     // hub rows

@@ -388,6 +388,38 @@ int compute_degrees(sphx_graph *g, double *d64, float *d32, void *scratch,
   return SPHX_OK;
 }
 
+namespace {
+
+// Column offsets from the row as int16, one thread per row; *overflow is
+// set when some offset does not fit (the offsets are then not used).
+__global__ __launch_bounds__(256) void k_delta16(int64_t n, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ col, int16_t *d,
+                                                 int *overflow) {
+  int f = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    for (int64_t k = rp[i]; k < (int64_t)rp[i + 1]; ++k) {
+      const int64_t o = (int64_t)col[k] - i;
+      const bool fits = o >= -32767 && o <= 32767;
+      d[k] = (int16_t)(fits ? o : 0);
+      f |= fits ? 0 : 1;
+    }
+  }
+  if (f) atomicOr(overflow, 1);
+}
+
+__global__ void k_fill_int(int *x, int cnt, int v) {
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) x[i] = v;
+}
+
+}  // namespace
+
+// the int16 column offsets are kept for unit-weight graphs with 32-bit row
+// pointers that are (or may be, before their degrees are known) unbinned
+static bool may_compress(const sphx_graph *g) {
+  return g->wdt == SPHX_UNIT && !g->rp64 && (!g->stats_valid || g->max_deg <= kUnbinnedMaxDeg);
+}
+
 size_t plan_bytes(sphx_graph *g) {
   int64_t n = g->n;
   int64_t nb = ceil_div(n, kBinRows);
@@ -399,6 +431,7 @@ size_t plan_bytes(sphx_graph *g) {
   b += align_up(sizeof(int64_t) * max_chunks, 256) * 2; // chunk ranges
   b += align_up(sizeof(double) * max_chunks * kMaxNev, 256);
   b += align_up(sizeof(int) * (nb * kNumCls + kNumCls), 256);
+  if (may_compress(g)) b += align_up(sizeof(int16_t) * g->nnz, 256) + 256;
   return b + 4096;
 }
 
@@ -417,6 +450,18 @@ int build_plan(sphx_graph *g, Arena &ws, SpmmPlan *plan, const DegreeStats &st,
   int *counts = ws.take<int>(nb * kNumCls + kNumCls);
   if (st.max_deg <= kUnbinnedMaxDeg) {   // natural order, one group size
     plan->group = st.max_deg <= bin_max_deg(0) ? bin_group(0) : bin_group(1);
+    if (may_compress(g) && g->nnz > 0) {
+      int16_t *d = ws.take<int16_t>(g->nnz);
+      int *flag = ws.take<int>(4);
+      hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, flag, 4, 0);
+      hipLaunchKernelGGL(k_delta16, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n,
+                         (const int32_t *)g->rowptr, g->col, d, flag);
+      SPHX_HIP(g->h, hipGetLastError());
+      int *hf = static_cast<int *>(pinned);
+      SPHX_HIP(g->h, hipMemcpyAsync(hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      SPHX_HIP(g->h, hipStreamSynchronize(s));
+      if (hf[0] == 0) plan->dcol = d;
+    }
     return SPHX_OK;
   }
   plan->binned = true;

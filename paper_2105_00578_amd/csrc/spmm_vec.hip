@@ -41,11 +41,25 @@ template <> struct Vec<double, 16> {
   static constexpr int E = 2;
 };
 
+// Unit weights with the column indices stored as int16 offsets from the row
+// (graphs whose every neighbour lies within 32767 rows: two bytes per entry
+// instead of four in the index stream).
+struct UnitD16 {};
+template <typename WT>
+constexpr bool kUnitW = std::is_same_v<WT, Unit> || std::is_same_v<WT, UnitD16>;
+template <typename WT> struct ColOf { using type = int32_t; };
+template <> struct ColOf<UnitD16> { using type = int16_t; };
+
 template <typename IdxT, typename WT>
 struct Csr {
   const IdxT *rp;
-  const int32_t *col;
+  const typename ColOf<WT>::type *col;
   const WT *w;
+  // neighbour of row i stored at entry k
+  __device__ __forceinline__ int64_t nbr(int64_t i, int64_t k) const {
+    if constexpr (std::is_same_v<WT, UnitD16>) return i + (int64_t)col[k];
+    else return (int64_t)col[k];
+  }
 };
 
 // Block id remap: XCD x = b % 8 receives a contiguous range of block ids.
@@ -59,7 +73,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
 // U independent partial sums (U gathers in flight per lane), combined in a
 // fixed order.
 template <typename T, int VB, int NV, typename IdxT, typename WT>
-__device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t k0, int64_t k1,
+__device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t i, int64_t k0, int64_t k1,
                                          int step, const typename Vec<T, VB>::type *__restrict__ X,
                                          int ldv, const typename Vec<T, VB>::type (&xi)[NV],
                                          typename Vec<T, VB>::type (&acc)[NV]) {
@@ -74,7 +88,7 @@ __device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t k0, int
   for (; k + (U - 1) * step < k1; k += U * step) {
     int64_t j[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) j[u] = A.col[k + u * step];
+    for (int u = 0; u < U; ++u) j[u] = A.nbr(i, k + u * step);
     V x[U][NV];
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -82,7 +96,7 @@ __device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t k0, int
       for (int v = 0; v < NV; ++v) x[u][v] = X[j[u] * ldv + v];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if constexpr (std::is_same_v<WT, Unit>) {
+      if constexpr (kUnitW<WT>) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) a[u][v] += xi[v] - x[u][v];
       } else {
@@ -96,8 +110,8 @@ __device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t k0, int
 #pragma unroll
   for (int u = 0; u < U - 1; ++u) {
     if (k < k1) {
-      const int64_t j0 = A.col[k];
-      if constexpr (std::is_same_v<WT, Unit>) {
+      const int64_t j0 = A.nbr(i, k);
+      if constexpr (kUnitW<WT>) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) a[u][v] += xi[v] - X[j0 * ldv + v];
       } else {
@@ -273,7 +287,7 @@ __global__ __launch_bounds__(256) void k_vrow(Csr<IdxT, WT> A, const int32_t *__
     V xi[NV], acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
-    vrow_acc<T, VB, NV>(A, (int64_t)A.rp[i], (int64_t)A.rp[i + 1], 1, X, ldv, xi, acc);
+    vrow_acc<T, VB, NV>(A, i, (int64_t)A.rp[i], (int64_t)A.rp[i + 1], 1, X, ldv, xi, acc);
     epi.row(i, xi, acc, n1, n2);
   }
   if constexpr (Epi::kNorms) block_norms<LD>(n1, n2, m, partials, slot0 + (int)blockIdx.x);
@@ -332,7 +346,7 @@ __global__ __launch_bounds__(256) void k_vgroup(Csr<IdxT, WT> A,
     V xi[NV], acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
-    vrow_acc<T, VB, NV>(A, (int64_t)A.rp[i] + gl, (int64_t)A.rp[i + 1], G, X, ldv, xi, acc);
+    vrow_acc<T, VB, NV>(A, i, (int64_t)A.rp[i] + gl, (int64_t)A.rp[i + 1], G, X, ldv, xi, acc);
     group_sum<T, VB, NV, G>(acc);
     if (gl == 0) epi.row(i, xi, acc, n1, n2);
   }
@@ -362,7 +376,7 @@ __global__ __launch_bounds__(256) void k_vhub_partial(
     V xi[NV], acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
-    vrow_acc<T, VB, NV>(A, k0s[q] + lane, k1s[q], 64, X, ldv, xi, acc);
+    vrow_acc<T, VB, NV>(A, i, k0s[q] + lane, k1s[q], 64, X, ldv, xi, acc);
     wave_sum<T, VB, NV>(acc);
     if (lane == 0)
 #pragma unroll
@@ -458,7 +472,7 @@ void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X
     // lane's serial walk over the row (one lane per row for unit weights, two
     // when a weight stream rides along); narrow rows take four lanes
     int G = plan.group;
-    if (G > 1 && VB * NV >= 32) G = std::is_same_v<WT, Unit> ? 1 : 2;
+    if (G > 1 && VB * NV >= 32) G = kUnitW<WT> ? 1 : 2;
     if (G == 1) short_rows(nullptr, n, kMaxShortBlocks);
     else grouped(G, nullptr, n, kGroupBlocks);
   } else {
@@ -490,8 +504,10 @@ int dispatch_types(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, cons
   auto go = [&](auto idx_tag, auto w_tag) {
     using IdxT = decltype(idx_tag);
     using WT = decltype(w_tag);
-    Csr<IdxT, WT> A{static_cast<const IdxT *>(g->rowptr), g->col,
-                    static_cast<const WT *>(g->w)};
+    const typename ColOf<WT>::type *col;
+    if constexpr (std::is_same_v<WT, UnitD16>) col = plan.dcol;
+    else col = g->col;
+    Csr<IdxT, WT> A{static_cast<const IdxT *>(g->rowptr), col, static_cast<const WT *>(g->w)};
     EpiT<T, VB, NV> epi{p};
     if constexpr (std::is_same_v<EpiT<T, VB, NV>, VResidual<T, VB, NV>>) epi.m = m;
     run_vec<T, VB, NV>(A, g->n, plan, X, ld, epi, partials, nparts, m, s, ev);
@@ -501,7 +517,8 @@ int dispatch_types(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, cons
     else if (g->wdt == SPHX_F32) go(int64_t{}, float{});
     else go(int64_t{}, double{});
   } else {
-    if (g->wdt == SPHX_UNIT) go(int32_t{}, Unit{});
+    if (g->wdt == SPHX_UNIT && plan.dcol) go(int32_t{}, UnitD16{});
+    else if (g->wdt == SPHX_UNIT) go(int32_t{}, Unit{});
     else if (g->wdt == SPHX_F32) go(int32_t{}, float{});
     else go(int32_t{}, double{});
   }

@@ -145,3 +145,39 @@ def test_spmm_full_size_grid128_sampled(handle):
         assert np.all(np.abs(Y[i] - ref) <= bound + 1e-300)
     C = torch.ones((g.n, 7), dtype=torch.float32, device=dev())
     assert torch.count_nonzero(sx.laplacian_apply(handle, G, C)) == 0
+
+
+def _path_plus(n, extra):
+    u = np.concatenate([np.arange(n - 1), [extra[0]]])
+    v = np.concatenate([np.arange(1, n), [extra[1]]])
+    return graphgen.csr_from_edges(n, u, v)
+
+
+@pytest.mark.parametrize("case,bytes_", [("fits", 2), ("overflows", 4), ("permuted", 4),
+                                         ("grid", 2)])
+def test_int16_column_offsets(handle, case, bytes_):
+    """Unit-weight graphs of at most 48 neighbours per row are read through
+    int16 offsets from the row when every offset fits (|offset| <= 32767),
+    else through the int32 columns; both give the oracle's product."""
+    if case == "fits":
+        g = _path_plus(40000, (5, 5 + 32767))
+    elif case == "overflows":
+        g = _path_plus(40000, (5, 5 + 32768))
+    else:
+        n, (u, v) = graphgen.grid3d_7pt(40, 40, 40)
+        if case == "permuted":
+            p = np.random.default_rng(2).permutation(n)
+            u, v = p[u], p[v]
+        g = graphgen.csr_from_edges(n, u, v)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    for dtype, m in ((torch.float32, 4), (torch.float32, 8), (torch.float64, 2)):
+        X = graphgen.normal_block(g.n, m, 5).astype(np.float32 if dtype == torch.float32
+                                                    else np.float64)
+        Y = sx.laplacian_apply(handle, G, torch.from_numpy(X).to(dev())).cpu().numpy()
+        ref = lap.apply(g.rowptr, g.col, None, X.astype(np.float64))
+        eps = 2.0 ** -24 if dtype == torch.float32 else 2.0 ** -53
+        assert np.all(np.abs(Y - ref) <= _bound(g, X.astype(np.float64), eps))
+    opts = sx.Options(precond=sx.PRECOND_JACOBI, tol=1e-2, precision=sx.MIXED, max_iter=3)
+    _, _, st = sx.eigensolve(handle, G, 3, opts, allow_not_converged=True)
+    assert st.col_index_bytes == bytes_

@@ -359,8 +359,9 @@ int eig_backward(sphx_graph *g, const SpmmPlan &plan, int problem, int nev,
     gram_small(V, gV, nullptr, Mdev);
     hipLaunchKernelGGL(k_project_rhs, dim3(grid_for(blk, 256, 4096)), dim3(256), 0, s, gV, V,
                        bd, (const double *)Mdev, n, nev, F);
-    hipMemsetAsync(MU, 0, sizeof(double) * blk, s);
-    hipMemcpyAsync(Rr, F, sizeof(double) * blk, hipMemcpyDeviceToDevice, s);
+    if (hipMemsetAsync(MU, 0, sizeof(double) * blk, s) != hipSuccess ||
+        hipMemcpyAsync(Rr, F, sizeof(double) * blk, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return SPHX_E_HIP;
     auto precond = [&]() {
       hipLaunchKernelGGL(k_jac, dim3(grid_for(blk, 256, 4096)), dim3(256), 0, s,
                          (const double *)Rr, d64, bd, prm, n, Z);
@@ -369,7 +370,8 @@ int eig_backward(sphx_graph *g, const SpmmPlan &plan, int problem, int nev,
                          (const double *)Mdev, n, nev);
     };
     precond();
-    hipMemcpyAsync(Pp, Z, sizeof(double) * blk, hipMemcpyDeviceToDevice, s);
+    if (hipMemcpyAsync(Pp, Z, sizeof(double) * blk, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return SPHX_E_HIP;
     double rz[kMaxNev], f2[kMaxNev], r2[kMaxNev], pap[kMaxNev];
     SPHX_TRY(coldot(Rr, Z, host));
     for (int k = 0; k < nev; ++k) rz[k] = host[k];

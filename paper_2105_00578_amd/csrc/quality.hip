@@ -142,8 +142,11 @@ int quality(sphx_graph *g, const int32_t *part, int K, double *cut, double *imba
   int e0 = 0;
   if (g->wdt == SPHX_F32) e0 = fixed_exponent<float>(g->wmin);
   if (g->wdt == SPHX_F64) e0 = fixed_exponent<double>(g->wmin);
-  hipMemsetAsync(pw, 0, sizeof(unsigned long long) * K, s);
-  hipMemsetAsync(bad, 0, sizeof(int) * 4, s);
+  if (hipMemsetAsync(pw, 0, sizeof(unsigned long long) * K, s) != hipSuccess ||
+      hipMemsetAsync(bad, 0, sizeof(int) * 4, s) != hipSuccess) {
+    *err = "quality: memset failed";
+    return SPHX_E_HIP;
+  }
   hipLaunchKernelGGL(k_part_weights, dim3(grid_for(g->n, 256 * 16, 1024)), dim3(256), 0, s,
                      g->n, part, g->vwgt, K, pw, bad);
   const unsigned nb = grid_for(g->nnz, kCutChunk, kCutBlocks);

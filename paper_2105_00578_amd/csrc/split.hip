@@ -263,10 +263,10 @@ int split_mj(sphx_graph *g, const T *coords, int ld, int ncoord, int K, int32_t 
   long long *Wnext = a.take<long long>(K);
   int *incl = a.take<int>(K);
   int *flag = a.take<int>(4);
-  hipMemsetAsync(part, 0, sizeof(int32_t) * n, s);
-  hipMemsetAsync(hist, 0, sizeof(unsigned long long) * (size_t)K * 256, s);
-  hipMemsetAsync(W, 0, sizeof(long long) * K, s);
-  hipMemsetAsync(flag, 0, sizeof(int) * 4, s);
+  bool ok = hipMemsetAsync(part, 0, sizeof(int32_t) * n, s) == hipSuccess;
+  ok &= hipMemsetAsync(hist, 0, sizeof(unsigned long long) * (size_t)K * 256, s) == hipSuccess;
+  ok &= hipMemsetAsync(W, 0, sizeof(long long) * K, s) == hipSuccess;
+  ok &= hipMemsetAsync(flag, 0, sizeof(int) * 4, s) == hipSuccess;
   hipLaunchKernelGGL(k_wsum, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, n, g->vwgt, W);
   const int nd = (int)sizeof(KT) + 4;
   const unsigned gn = grid_for(n, 256, 4096);
@@ -295,15 +295,16 @@ int split_mj(sphx_graph *g, const T *coords, int ld, int ncoord, int K, int32_t 
     hipLaunchKernelGGL((k_assign<KT>), dim3(gn), dim3(256), 0, s, n, keys, part, p, pord, pid,
                        incl, W);
     nsec *= p;
-    hipMemcpyAsync(W, Wnext, sizeof(long long) * nsec, hipMemcpyDeviceToDevice, s);
+    ok &= hipMemcpyAsync(W, Wnext, sizeof(long long) * nsec, hipMemcpyDeviceToDevice, s) ==
+          hipSuccess;
   }
-  if (hipGetLastError() != hipSuccess) {
+  if (!ok || hipGetLastError() != hipSuccess) {
     *err = "split kernel launch failed";
     return SPHX_E_HIP;
   }
   int *fh = static_cast<int *>(pinned);
-  hipMemcpyAsync(fh, flag, sizeof(int), hipMemcpyDeviceToHost, s);
-  if (hipStreamSynchronize(s) != hipSuccess) {
+  if (hipMemcpyAsync(fh, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
     *err = "split: stream error";
     return SPHX_E_HIP;
   }

@@ -253,6 +253,7 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double *partials, int
 
 // --------------------------------------------------------- Rayleigh-Ritz
 constexpr int LDA = kMaxW + 1;
+static_assert(kMaxW < 64, "Rayleigh-Ritz pivot search: one candidate per lane of a wave");
 
 // Cyclic Jacobi eigensolver (round-robin parallel ordering) on the k x k
 // symmetric matrix A (LDS, stride LDA); V receives the eigenvectors.
@@ -381,16 +382,26 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
     // ---- pivoted Cholesky of Gs
     int k = 0;
     for (; k < wl; ++k) {
-      if (t == 0) {
-        int best = -1;
-        double bv = 0.0;
-        for (int j = 0; j < wl; ++j)
-          if (ipiv[j] < 0 && M1[j * LDA + j] > bv) { bv = M1[j * LDA + j]; best = j; }
-        pstep = (best >= 0 && bv > a.drop_tol) ? best : -1;
-        pval = bv;
-        if (pstep >= 0) {
-          piv[k] = best;
-          ipiv[best] = k;
+      if (t < 64) {
+        // pivot: the largest positive remaining diagonal entry, the lowest
+        // index on ties (wave 0, one candidate per lane: wl <= kMaxW < 64)
+        double bv = (t < wl && ipiv[t] < 0) ? M1[t * LDA + t] : 0.0;
+        int best = bv > 0.0 ? t : -1;
+        for (int off = 32; off >= 1; off >>= 1) {
+          const double ov = __shfl_xor(bv, off);
+          const int ob = __shfl_xor(best, off);
+          if (ob >= 0 && (best < 0 || ov > bv || (ov == bv && ob < best))) {
+            bv = ov;
+            best = ob;
+          }
+        }
+        if (t == 0) {
+          pstep = (best >= 0 && bv > a.drop_tol) ? best : -1;
+          pval = bv;
+          if (pstep >= 0) {
+            piv[k] = best;
+            ipiv[best] = k;
+          }
         }
       }
       __syncthreads();

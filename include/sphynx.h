@@ -104,6 +104,16 @@ typedef struct sphx_options {
     double drop_tol;      /* Rayleigh-Ritz basis directions with relative
                              Gram eigenvalue below this are dropped; 0 picks
                              1e-10 (MIXED) or 1e-14 (FP64)                   */
+    int promote_window;   /* MIXED only.  FP32 vectors cannot get closer to
+                             an eigenvector than their rounding, so a
+                             tolerance near that floor can stall: when, over
+                             this many iterations, neither an eigenpair
+                             converged nor the largest unconverged rho_i fell
+                             below 0.7 of its value at the last such
+                             progress, the iteration continues in FP64 from
+                             the current vectors (stats.promoted = 1; the
+                             returned vectors stay FP32).  0 = 100,
+                             < 0 = never.                                     */
 } sphx_options;
 
 typedef struct sphx_stats {
@@ -130,6 +140,9 @@ typedef struct sphx_stats {
                                     once (gathered rows counted once)         */
     int64_t precond_cols; /* sum over preconditioner applies of the number of
                              active (unconverged) columns they served         */
+    int32_t promoted;     /* 1 if a MIXED solve continued in FP64 (see
+                             sphx_options.promote_window); iterations count
+                             both parts                                       */
     int32_t col_index_bytes; /* bytes per column index the vector products
                                 read: 2 when the graph (unit weights, 32-bit
                                 row pointers, at most 48 neighbours per row,

@@ -28,7 +28,7 @@ class _Options(C.Structure):
     _fields_ = [("problem", C.c_int), ("precond", C.c_int), ("cheb_degree", C.c_int),
                 ("cheb_ratio", C.c_double), ("precision", C.c_int), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("init", C.c_int), ("seed", C.c_uint64),
-                ("locking", C.c_int), ("drop_tol", C.c_double)]
+                ("locking", C.c_int), ("drop_tol", C.c_double), ("promote_window", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -41,7 +41,7 @@ class _Stats(C.Structure):
                 ("ms_quality", C.c_double), ("spmm_calls", C.c_int64),
                 ("precond_calls", C.c_int64), ("gb_spmm", C.c_double),
                 ("gb_precond", C.c_double), ("precond_cols", C.c_int64),
-                ("col_index_bytes", C.c_int32)]
+                ("promoted", C.c_int32), ("col_index_bytes", C.c_int32)]
 
 
 def _load():
@@ -135,6 +135,7 @@ class Options:
     seed: int = 0x5EED
     locking: int = 1
     drop_tol: float = 0.0
+    promote_window: int = 0
 
     def _c(self) -> _Options:
         return _Options(**dataclasses.asdict(self))
@@ -168,6 +169,7 @@ class Stats:
     gb_spmm: float
     gb_precond: float
     precond_cols: int
+    promoted: int
     col_index_bytes: int
 
 
@@ -177,7 +179,7 @@ def _stats(s: _Stats, nev: int) -> Stats:
     return Stats(s.iterations, s.converged, s.restarts, s.graph_regular, s.max_degree,
                  s.avg_degree, list(s.rho[: min(nev, 32)]), s.ms_total, phases,
                  s.spmm_calls, s.precond_calls, s.gb_spmm, s.gb_precond, s.precond_cols,
-                 s.col_index_bytes)
+                 s.promoted, s.col_index_bytes)
 
 
 def _torch():

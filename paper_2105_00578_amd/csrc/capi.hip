@@ -425,7 +425,7 @@ int poly_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, int l
 template <typename T>
 int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const void *X0,
           double *eigvals, T *vecs_out, sphx_stats *stats, SolveWs<T> &w, char *wsbase,
-          bool *hit_max) {
+          bool *hit_max, bool *stalled) {
   hipStream_t s = h->stream;
   const int64_t n = g->n;
   int64_t calls = 0, pcalls = 0, pcols = 0;
@@ -540,6 +540,17 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   // ---- iterations
   int it = 0, restarts = 0;
   bool have_p = false;
+  // FP32 stagnation watch (see sphx_options.promote_window)
+  const int window = o.promote_window == 0 ? 100 : o.promote_window;
+  const bool watch = std::is_same_v<T, float> && o.promote_window >= 0 && stalled;
+  auto worst_active = [&]() {
+    double r = 0.0;
+    for (int q = 0; q < hs->nact; ++q) r = std::max(r, hs->rho[hs->act[q]]);
+    return r;
+  };
+  int ref_nact = hs->nact, ref_it = 0;
+  double ref_rho = worst_active();
+  if (stalled) *stalled = false;
   while (hs->nact > 0 && it < o.max_iter) {
     ColMap act;
     act.count = hs->nact;
@@ -583,8 +594,19 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     if (hs->breakdown)
       return set_err(h, SPHX_E_BREAKDOWN,
                      "Rayleigh-Ritz basis rank deficient even without the P block");
+    if (watch && hs->nact > 0) {
+      const double wr = worst_active();
+      if (hs->nact < ref_nact || wr < 0.7 * ref_rho) {
+        ref_nact = hs->nact;
+        ref_rho = wr;
+        ref_it = it;
+      } else if (it - ref_it >= window) {
+        *stalled = true;
+        break;
+      }
+    }
   }
-  *hit_max = hs->nact > 0;
+  *hit_max = hs->nact > 0 && !(stalled && *stalled);
   // ---- final FP64 residual check and normalisation
   double *X64 = reinterpret_cast<double *>(w.X);
   double *LX64 = reinterpret_cast<double *>(w.LX);
@@ -726,6 +748,7 @@ void sphx_options_default(sphx_options *o, int regular, int precond) {
   o->seed = 0x5eed;
   o->locking = 1;
   o->drop_tol = 0.0;
+  o->promote_window = 0;
 }
 
 int sphx_graph_create(sphx_handle *h, int64_t n, int64_t nnz, const void *row_ptr,
@@ -796,16 +819,28 @@ static int poly_degree_of(const sphx_options *o) {
   return o->precond == SPHX_PRECOND_GMRES ? o->cheb_degree : 0;
 }
 
+// Bytes of the FP32 solve's layout; a MIXED solve keeps, after it, room for
+// an FP64 continuation (its own layout plus the n x nev initial and result
+// blocks), laid out from this offset.
+static size_t fp32_layout_bytes(sphx_graph *g, int nev, int K, bool split, int poly_degree) {
+  Arena a;
+  a.count_only = true;
+  SolveWs<float> w;
+  layout(a, w, g->n, nev, K, plan_bytes(g), split, poly_degree);
+  return align_up(a.off, 256);
+}
+
 static size_t solve_bytes(sphx_graph *g, int nev, int precision, int K, bool split,
                           int poly_degree) {
   Arena a;
   a.count_only = true;
   size_t pb = plan_bytes(g);
+  SolveWs<double> w;
   if (precision == SPHX_MIXED) {
-    SolveWs<float> w;
-    layout(a, w, g->n, nev, K, pb, split, poly_degree);
+    a.off = fp32_layout_bytes(g, nev, K, split, poly_degree);
+    layout(a, w, g->n, nev, K, pb, false, poly_degree);
+    (void)a.take<double>((size_t)g->n * nev * 2);
   } else {
-    SolveWs<double> w;
     layout(a, w, g->n, nev, K, pb, split, poly_degree);
   }
   return a.off + 4096;
@@ -1134,7 +1169,42 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
     layout(a, w, g->n, nev, std::max(K, 1), plan_bytes(g), split, poly_degree_of(o));
     T *vecs = eigvecs ? static_cast<T *>(eigvecs) : w.V;
     if (!vecs) return set_err(h, SPHX_E_INVALID_ARG, "eigvecs is NULL");
-    SPHX_TRY(solve<T>(h, g, nev, *o, X0, eigvals, vecs, stats, w, ws, &hit_max));
+    bool stalled = false;
+    SPHX_TRY(solve<T>(h, g, nev, *o, X0, eigvals, vecs, stats, w, ws, &hit_max, &stalled));
+    if constexpr (std::is_same_v<T, float>) {
+      if (stalled) {
+        // continue in FP64 from the current vectors (their normalised form,
+        // in y for the normalized problem, is exactly an initial block)
+        Arena a64;
+        a64.base = ws + fp32_layout_bytes(g, nev, std::max(K, 1), split, poly_degree_of(o));
+        SolveWs<double> w64;
+        layout(a64, w64, g->n, nev, std::max(K, 1), plan_bytes(g), false,
+               poly_degree_of(o));
+        double *x0 = a64.take<double>((size_t)g->n * nev);
+        double *v64 = a64.take<double>((size_t)g->n * nev);
+        launch_convert<float, double>(vecs, x0, (int64_t)g->n * nev, h->stream);
+        sphx_options o64 = *o;
+        o64.precision = SPHX_FP64;
+        o64.init = SPHX_INIT_USER;
+        o64.drop_tol = 0.0;
+        sphx_stats s64;
+        std::memset(&s64, 0, sizeof(s64));
+        SPHX_TRY(solve<double>(h, g, nev, o64, x0, eigvals, v64, stats ? &s64 : nullptr, w64,
+                               (char *)a64.base, &hit_max, nullptr));
+        launch_convert<double, float>(v64, vecs, (int64_t)g->n * nev, h->stream);
+        if (stats) {
+          stats->iterations += s64.iterations;
+          stats->converged = s64.converged;
+          stats->restarts += s64.restarts;
+          for (int q = 0; q < 32; ++q) stats->rho[q] = s64.rho[q];
+          stats->spmm_calls += s64.spmm_calls;
+          stats->precond_calls += s64.precond_calls;
+          stats->precond_cols += s64.precond_cols;
+          stats->ms_total += s64.ms_total;
+          stats->promoted = 1;
+        }
+      }
+    }
     if (split) {
       Timer ts;
       if (stats) ts.start(h->stream);

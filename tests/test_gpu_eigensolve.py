@@ -155,3 +155,55 @@ def test_rank_deficient_start_recovers_or_reports(handle):
     with pytest.raises(sx.SphynxError) as e:
         sx.eigensolve(handle, G, 3, opts, X0)
     assert e.value.code == -6            # SPHX_E_BREAKDOWN
+
+
+# ---- MIXED stagnation -> FP64 continuation
+
+def test_mixed_promotes_when_tol_is_below_the_fp32_floor(handle):
+    """tol 1e-9 is far below what FP32 vectors can reach: the MIXED solve
+    stalls, continues in FP64 and meets the tolerance; the returned vectors
+    are the FP64 result rounded to FP32."""
+    g = random_graph(400, 0.015, 21, np.float32)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    nev = 4
+    L, d = lap.dense(g.rowptr, g.col, g.w.astype(np.float64))
+    lam_ref, V_ref = eigen.smallest_dense(L, d, nev + 1)
+    opts = sx.Options(problem=sx.GENERALIZED, precond=sx.PRECOND_JACOBI, tol=1e-9,
+                      precision=sx.MIXED, seed=3, max_iter=3000, promote_window=20)
+    lam, V, st = sx.eigensolve(handle, G, nev, opts)
+    assert st.promoted == 1 and st.converged == nev
+    assert max(st.rho[:nev]) <= 1e-9
+    assert abs(lam[0]) <= 1e-9 * lam_ref[1]
+    assert np.allclose(lam[1:], lam_ref[1:nev], rtol=1e-9, atol=0)
+    Vh = V.cpu().numpy()
+    assert V.dtype == torch.float32
+    assert eigen.subspace_sin(Vh.astype(np.float64), V_ref[:, :nev], d) < 1e-5
+
+
+def test_mixed_promotion_off_and_default(handle):
+    g = random_graph(400, 0.015, 21, np.float32)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    opts = sx.Options(problem=sx.GENERALIZED, precond=sx.PRECOND_JACOBI, tol=1e-9,
+                      precision=sx.MIXED, seed=3, max_iter=300, promote_window=-1)
+    lam, V, st = sx.eigensolve(handle, G, 4, opts, allow_not_converged=True)
+    assert st.promoted == 0 and st.iterations == 300
+    # a reachable tolerance converges in FP32 with the default window
+    opts = sx.Options(problem=sx.GENERALIZED, precond=sx.PRECOND_JACOBI, tol=1e-3,
+                      precision=sx.MIXED, seed=3, max_iter=3000)
+    lam, V, st = sx.eigensolve(handle, G, 4, opts)
+    assert st.promoted == 0 and st.converged == 4
+
+
+def test_partition_after_promotion_splits_the_returned_vectors(handle):
+    from oracle import split
+    g = random_graph(500, 0.012, 4)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    opts = sx.Options(problem=sx.COMBINATORIAL, precond=sx.PRECOND_JACOBI, tol=1e-8,
+                      precision=sx.MIXED, seed=5, max_iter=3000, promote_window=10)
+    lam, V, part, cut, imb, st = sx.partition(handle, G, 8, opts)
+    assert st.promoted == 1
+    ref = split.split_mj(V.cpu().numpy()[:, 1:], 8)
+    assert np.array_equal(part.cpu().numpy(), ref)

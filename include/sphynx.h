@@ -114,6 +114,13 @@ typedef struct sphx_options {
                              the current vectors (stats.promoted = 1; the
                              returned vectors stay FP32).  0 = 100,
                              < 0 = never.                                     */
+    int reorder;          /* 1 (default): graphs with rows of more than 48
+                             neighbours are solved on a copy whose rows are
+                             ordered by floor(log2 degree), descending (ties
+                             by id), so that the frequently gathered rows of
+                             high degree share cache lines; initial blocks and
+                             results stay in the caller's order.  0: the
+                             caller's order.                                  */
 } sphx_options;
 
 typedef struct sphx_stats {

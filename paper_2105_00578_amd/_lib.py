@@ -28,7 +28,8 @@ class _Options(C.Structure):
     _fields_ = [("problem", C.c_int), ("precond", C.c_int), ("cheb_degree", C.c_int),
                 ("cheb_ratio", C.c_double), ("precision", C.c_int), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("init", C.c_int), ("seed", C.c_uint64),
-                ("locking", C.c_int), ("drop_tol", C.c_double), ("promote_window", C.c_int)]
+                ("locking", C.c_int), ("drop_tol", C.c_double), ("promote_window", C.c_int),
+                ("reorder", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -136,6 +137,7 @@ class Options:
     locking: int = 1
     drop_tol: float = 0.0
     promote_window: int = 0
+    reorder: int = 1
 
     def _c(self) -> _Options:
         return _Options(**dataclasses.asdict(self))

@@ -54,7 +54,8 @@ struct SolveWs {
   int *flags;
   void *split_scratch, *quality_scratch;
   void *poly_scratch;   // Lanczos basis of the GMRES polynomial (or null)
-  double *poly_b;
+  double *poly_b, *poly_tmp;
+  char *ord_scratch;    // degree-ordered copy of the graph (or null)
   T *V;        // eigenvectors when the caller passes none (partition)
   int32_t *part;
   SpmmPlan plan;
@@ -63,7 +64,7 @@ struct SolveWs {
 
 template <typename T>
 void layout(Arena &a, SolveWs<T> &w, int64_t n, int m, int K, size_t plan_b,
-            bool want_split, int poly_degree) {
+            bool want_split, int poly_degree, size_t ord_b) {
   w.d64 = a.take<double>(n);
   w.dinv = a.take<double>(n);
   w.sq = a.take<double>(n);
@@ -108,12 +109,26 @@ void layout(Arena &a, SolveWs<T> &w, int64_t n, int m, int K, size_t plan_b,
   if (poly_degree > 0) {
     w.poly_scratch = a.take<char>(poly_scratch_bytes(n, poly_degree));
     w.poly_b = a.take<double>(n);
+    w.poly_tmp = a.take<double>(n);
   } else {
     w.poly_scratch = nullptr;
-    w.poly_b = nullptr;
+    w.poly_b = w.poly_tmp = nullptr;
   }
+  w.ord_scratch = ord_b ? a.take<char>(ord_b) : nullptr;
   w.plan_off = a.off;
   a.off += plan_b;
+}
+
+// dst row i (m values) = src row idx[i]
+template <typename T>
+__global__ void k_gather_rows(const T *__restrict__ src, int lds, const int32_t *__restrict__ idx,
+                              T *dst, int ldd, int64_t n, int m) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / m;
+    const int c = (int)(e - i * m);
+    dst[i * ldd + c] = src[(int64_t)idx[i] * lds + c];
+  }
 }
 
 bool valid_options(const sphx_options *o) {
@@ -130,6 +145,7 @@ bool valid_options(const sphx_options *o) {
   if (!(o->tol > 0.0) || o->max_iter < 0) return false;
   if (o->init < SPHX_INIT_RANDOM || o->init > SPHX_INIT_USER) return false;
   if (o->drop_tol < 0.0) return false;
+  if (o->reorder != 0 && o->reorder != 1) return false;
   return true;
 }
 
@@ -436,6 +452,18 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   int tid = pl.begin(PH_SETUP, 0.0, s);
   DegreeStats ds;
   SPHX_TRY(compute_degrees(g, w.d64, nullptr, w.deg_scratch, &ds, h->pinned_small, s));
+  // graphs with rows of more than kUnbinnedMaxDeg neighbours run on a copy in
+  // degree order (frequently gathered rows share cache lines); blocks live
+  // in that order and are mapped at the start and the end of the solve
+  sphx_graph gq;
+  sphx_graph *G = g;
+  int32_t *operm = nullptr, *oinv = nullptr;
+  const bool reorder = o.reorder && ds.max_deg > kUnbinnedMaxDeg && w.ord_scratch;
+  if (reorder) {
+    SPHX_TRY(build_degree_order(g, w.ord_scratch, &gq, &operm, &oinv, s));
+    G = &gq;
+    SPHX_TRY(compute_degrees(G, w.d64, nullptr, w.deg_scratch, &ds, h->pinned_small, s));
+  }
   // the normalized problem runs as the generalized pencil in x = D^-1/2 y
   const bool norm = o.problem == SPHX_NORMALIZED;
   const bool gen = o.problem != SPHX_COMBINATORIAL;
@@ -448,8 +476,8 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
                        w.rsq, n);
   Arena pa;
   pa.base = wsbase + w.plan_off;
-  pa.cap = plan_bytes(g);
-  SPHX_TRY(build_plan(g, pa, &w.plan, ds, h->pinned_small, s));
+  pa.cap = plan_bytes(G);
+  SPHX_TRY(build_plan(G, pa, &w.plan, ds, h->pinned_small, s));
   pl.end(tid, s);
   const int vs = sizeof(T);
   const int ld = padded_ld(m, sizeof(T));   // 16-byte rows for the vector kernels
@@ -470,13 +498,18 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   double roots[kMaxW];
   int nroots = 0;
   if (o.precond == SPHX_PRECOND_GMRES) {
-    launch_init_random<double>(w.poly_b, n, 1, 1, o.seed ^ 0x9e3779b97f4a7c15ull, s);
+    launch_init_random<double>(reorder ? w.poly_tmp : w.poly_b, n, 1, 1,
+                               o.seed ^ 0x9e3779b97f4a7c15ull, s);
+    if (reorder)
+      hipLaunchKernelGGL(k_gather_rows<double>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s,
+                         (const double *)w.poly_tmp, 1, (const int32_t *)operm, w.poly_b, 1,
+                         n, 1);
     if (norm)
       hipLaunchKernelGGL(k_scale_rows<double>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s,
                          (const double *)w.poly_b, (const double *)w.rsq, 1.0, w.poly_b, n, 1);
     std::string err;
     int id = pl.begin(PH_SETUP, 0.0, s);
-    int r = poly_roots(g, w.plan, gen, w.d64, dinv, w.poly_b, o.cheb_degree, roots, &nroots,
+    int r = poly_roots(G, w.plan, gen, w.d64, dinv, w.poly_b, o.cheb_degree, roots, &nroots,
                        w.poly_scratch, h->pinned_small, s, &err);
     pl.end(id, s);
     if (r != SPHX_OK) return set_err(h, r, err);
@@ -491,18 +524,24 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   const ColMap idm = identity_map(m);
   DevStatus *hs = h->pinned_status;
   // ---- initial block and Rayleigh-Ritz
+  T *Xi = reorder ? w.B2 : w.X;   // the initial block in the caller's order
   if (o.init == SPHX_INIT_USER) {
-    SPHX_HIP(h, hipMemsetAsync(w.X, 0, sizeof(T) * n * ld, s));
-    launch_copy_cols<T>(static_cast<const T *>(X0), m, w.X, ld, n, m, s);
+    SPHX_HIP(h, hipMemsetAsync(Xi, 0, sizeof(T) * n * ld, s));
+    launch_copy_cols<T>(static_cast<const T *>(X0), m, Xi, ld, n, m, s);
   } else if (o.init == SPHX_INIT_PIECEWISE)
-    launch_init_piecewise<T>(w.X, n, m, ld, s);
+    launch_init_piecewise<T>(Xi, n, m, ld, s);
   else
-    launch_init_random<T>(w.X, n, m, ld, o.seed, s);
+    launch_init_random<T>(Xi, n, m, ld, o.seed, s);
+  if (reorder) {
+    SPHX_HIP(h, hipMemsetAsync(w.X, 0, sizeof(T) * n * ld, s));
+    hipLaunchKernelGGL(k_gather_rows<T>, dim3(grid_for((int64_t)n * m, 256, 4096)), dim3(256),
+                       0, s, (const T *)Xi, ld, (const int32_t *)operm, w.X, ld, n, m);
+  }
   if (norm)   // the initial block is given in y; x = D^-1/2 y
     hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for((int64_t)n * ld, 256, 4096)), dim3(256),
                        0, s, (const T *)w.X, (const double *)w.rsq, 1.0, w.X, n, ld);
-  tid = pl.begin(PH_SPMM, spmm_bytes(g, w.plan, m, vs, 2, 0), s);
-  SPHX_TRY(vspmm_store<T>(g, w.plan, w.X, ld, m, EpiStoreP<T>{w.LX, ld}, s));
+  tid = pl.begin(PH_SPMM, spmm_bytes(G, w.plan, m, vs, 2, 0), s);
+  SPHX_TRY(vspmm_store<T>(G, w.plan, w.X, ld, m, EpiStoreP<T>{w.LX, ld}, s));
   pl.end(tid, s);
   ++calls;
   GramArgs ga{n, m, ld, idm, 0, 0, bdiag};
@@ -523,8 +562,8 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   auto residual = [&]() -> int {
     int nb = 0;
     EpiResidualP<T> er{w.LX, jac ? w.B1 : w.R, ld, w.theta, w.d64, gen ? 1 : 0, jac ? 1 : 0};
-    int id = pl.begin(PH_SPMM, spmm_bytes(g, w.plan, m, vs, 3, 1), s);
-    SPHX_TRY(vspmm_residual<T>(g, w.plan, w.X, ld, m, er, w.norm_partials, &nb, s));
+    int id = pl.begin(PH_SPMM, spmm_bytes(G, w.plan, m, vs, 3, 1), s);
+    SPHX_TRY(vspmm_residual<T>(G, w.plan, w.X, ld, m, er, w.norm_partials, &nb, s));
     pl.end(id, s);
     ++calls;
     id = pl.begin(PH_OTHER, 0.0, s);
@@ -558,16 +597,16 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     T *H = w.B1;
     pcols += act.count;
     if (o.precond == SPHX_PRECOND_CHEBYSHEV) {
-      SPHX_TRY(cheb_apply<T>(h, g, w.plan, m, ld, act, w.R, w.B1, w.B2, w.R, ck, dinv, s, &H,
+      SPHX_TRY(cheb_apply<T>(h, G, w.plan, m, ld, act, w.R, w.B1, w.B2, w.R, ck, dinv, s, &H,
                              &calls, &pcalls));
     } else if (o.precond == SPHX_PRECOND_GMRES) {
-      SPHX_TRY(poly_apply<T>(h, g, w.plan, m, ld, act, w.R, w.B1, w.B2, w.R, roots, nroots,
+      SPHX_TRY(poly_apply<T>(h, G, w.plan, m, ld, act, w.R, w.B1, w.B2, w.R, roots, nroots,
                              dinv, s, &H, &calls, &pcalls));
     } else if (o.precond == SPHX_PRECOND_NONE) {
       H = w.R;
     }
-    tid = pl.begin(PH_SPMM, spmm_bytes(g, w.plan, act.count, vs, 2, 0), s);
-    SPHX_TRY(vspmm_store<T>(g, w.plan, H, ld, m, EpiStoreP<T>{w.LH, ld}, s));
+    tid = pl.begin(PH_SPMM, spmm_bytes(G, w.plan, act.count, vs, 2, 0), s);
+    SPHX_TRY(vspmm_store<T>(G, w.plan, H, ld, m, EpiStoreP<T>{w.LH, ld}, s));
     pl.end(tid, s);
     ++calls;
     GramArgs gb{n, m, ld, act, 1, have_p ? 1 : 0, bdiag};
@@ -614,7 +653,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     launch_convert<float, double>(w.X, w.X64, n * ld, s);
     X64 = w.X64;
     LX64 = w.LX64;
-    SPHX_TRY(vspmm_store<double>(g, w.plan, X64, ld, m, EpiStoreP<double>{LX64, ld}, s));
+    SPHX_TRY(vspmm_store<double>(G, w.plan, X64, ld, m, EpiStoreP<double>{LX64, ld}, s));
     ++calls;
   }
   int rb = (int)grid_for(n, 256 / ld, kRqBlocks);
@@ -649,11 +688,15 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     if (rho <= o.tol) ++nconv;
     scale[q] = rs[kMaxNev + c] > 0 ? 1.0 / std::sqrt(rs[kMaxNev + c]) : 1.0;
   }
+  T *vo = reorder ? w.B2 : vecs_out;   // n x m in the solver's row order
   for (int q = 0; q < m; ++q)
-    launch_copy_cols<T>(w.X + perm[q], ld, vecs_out + q, m, n, 1, s);
+    launch_copy_cols<T>(w.X + perm[q], ld, vo + q, m, n, 1, s);
   if (norm)   // y = D^1/2 x; ||y||_2 = ||x||_D, so the same scale normalises y
     hipLaunchKernelGGL(k_scale_rows<T>, dim3(grid_for((int64_t)n * m, 256, 4096)), dim3(256),
-                       0, s, (const T *)vecs_out, (const double *)w.sq, 1.0, vecs_out, n, m);
+                       0, s, (const T *)vo, (const double *)w.sq, 1.0, vo, n, m);
+  if (reorder)
+    hipLaunchKernelGGL(k_gather_rows<T>, dim3(grid_for((int64_t)n * m, 256, 4096)), dim3(256),
+                       0, s, (const T *)vo, m, (const int32_t *)oinv, vecs_out, m, n, m);
   SPHX_TRY(normalize_columns<T>(vecs_out, n, m, scale, w.norm_scratch, s));
   if (stats) {
     stats->iterations = it;
@@ -749,6 +792,7 @@ void sphx_options_default(sphx_options *o, int regular, int precond) {
   o->locking = 1;
   o->drop_tol = 0.0;
   o->promote_window = 0;
+  o->reorder = 1;
 }
 
 int sphx_graph_create(sphx_handle *h, int64_t n, int64_t nnz, const void *row_ptr,
@@ -822,26 +866,34 @@ static int poly_degree_of(const sphx_options *o) {
 // Bytes of the FP32 solve's layout; a MIXED solve keeps, after it, room for
 // an FP64 continuation (its own layout plus the n x nev initial and result
 // blocks), laid out from this offset.
-static size_t fp32_layout_bytes(sphx_graph *g, int nev, int K, bool split, int poly_degree) {
+static size_t fp32_layout_bytes(sphx_graph *g, int nev, int K, bool split, int poly_degree,
+                                size_t ord_b) {
   Arena a;
   a.count_only = true;
   SolveWs<float> w;
-  layout(a, w, g->n, nev, K, plan_bytes(g), split, poly_degree);
+  layout(a, w, g->n, nev, K, plan_bytes(g), split, poly_degree, ord_b);
   return align_up(a.off, 256);
 }
 
+// room for the degree-ordered copy of the graph: while the degrees are not
+// known yet, whenever the option asks for it
+static size_t ord_bytes_of(sphx_graph *g, const sphx_options *o) {
+  const bool may = o->reorder && (!g->stats_valid || g->max_deg > kUnbinnedMaxDeg);
+  return may ? degree_order_bytes(g) : 0;
+}
+
 static size_t solve_bytes(sphx_graph *g, int nev, int precision, int K, bool split,
-                          int poly_degree) {
+                          int poly_degree, size_t ord_b) {
   Arena a;
   a.count_only = true;
   size_t pb = plan_bytes(g);
   SolveWs<double> w;
   if (precision == SPHX_MIXED) {
-    a.off = fp32_layout_bytes(g, nev, K, split, poly_degree);
-    layout(a, w, g->n, nev, K, pb, false, poly_degree);
+    a.off = fp32_layout_bytes(g, nev, K, split, poly_degree, ord_b);
+    layout(a, w, g->n, nev, K, pb, false, poly_degree, ord_b);
     (void)a.take<double>((size_t)g->n * nev * 2);
   } else {
-    layout(a, w, g->n, nev, K, pb, split, poly_degree);
+    layout(a, w, g->n, nev, K, pb, split, poly_degree, ord_b);
   }
   return a.off + 4096;
 }
@@ -850,7 +902,8 @@ int sphx_workspace_size(sphx_handle *h, sphx_graph *g, int nev, const sphx_optio
                         size_t *bytes) {
   if (!h || !g || !opt || !bytes || nev < 1 || nev > kMaxNev) return SPHX_E_INVALID_ARG;
   int K = 1 << (nev - 1);
-  size_t a = solve_bytes(g, nev, opt->precision, K, true, poly_degree_of(opt));
+  size_t a = solve_bytes(g, nev, opt->precision, K, true, poly_degree_of(opt),
+                         ord_bytes_of(g, opt));
   size_t b = adjoint_scratch_bytes(g->n, nev) + plan_bytes(g) + sizeof(double) * 2 * g->n +
              4096;
   *bytes = std::max(a, b);
@@ -1157,8 +1210,11 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
   h->plog.on = h->timing && stats;
   const bool split = part != nullptr;
   char *ws = nullptr;
-  SPHX_TRY(get_workspace(
-      h, solve_bytes(g, nev, o->precision, std::max(K, 1), split, poly_degree_of(o)), &ws));
+  const size_t ord_b = ord_bytes_of(g, o);
+  SPHX_TRY(get_workspace(h,
+                         solve_bytes(g, nev, o->precision, std::max(K, 1), split,
+                                     poly_degree_of(o), ord_b),
+                         &ws));
   bool hit_max = false;
   int st;
   auto run = [&](auto tag) -> int {
@@ -1166,7 +1222,8 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
     Arena a;
     a.base = ws;
     SolveWs<T> w;
-    layout(a, w, g->n, nev, std::max(K, 1), plan_bytes(g), split, poly_degree_of(o));
+    layout(a, w, g->n, nev, std::max(K, 1), plan_bytes(g), split, poly_degree_of(o), ord_b);
+    const size_t used = align_up(a.off, 256);   // the FP64 continuation starts here
     T *vecs = eigvecs ? static_cast<T *>(eigvecs) : w.V;
     if (!vecs) return set_err(h, SPHX_E_INVALID_ARG, "eigvecs is NULL");
     bool stalled = false;
@@ -1176,10 +1233,10 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
         // continue in FP64 from the current vectors (their normalised form,
         // in y for the normalized problem, is exactly an initial block)
         Arena a64;
-        a64.base = ws + fp32_layout_bytes(g, nev, std::max(K, 1), split, poly_degree_of(o));
+        a64.base = ws + used;
         SolveWs<double> w64;
         layout(a64, w64, g->n, nev, std::max(K, 1), plan_bytes(g), false,
-               poly_degree_of(o));
+               poly_degree_of(o), ord_b);
         double *x0 = a64.take<double>((size_t)g->n * nev);
         double *v64 = a64.take<double>((size_t)g->n * nev);
         launch_convert<float, double>(vecs, x0, (int64_t)g->n * nev, h->stream);

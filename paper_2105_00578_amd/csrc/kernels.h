@@ -56,6 +56,12 @@ int compute_degrees(sphx_graph *g, double *d64, float *d32, void *scratch,
 int build_plan(sphx_graph *g, Arena &ws, SpmmPlan *plan, const DegreeStats &st,
                void *pinned, hipStream_t s);
 size_t plan_bytes(sphx_graph *g);
+// Degree order of a graph: rows sorted by floor(log2 degree), descending,
+// ties in increasing id.  *out is a copy of g over permuted arrays in
+// scratch (degree_order_bytes(g)); perm[new] = old, inv[old] = new.
+size_t degree_order_bytes(const sphx_graph *g);
+int build_degree_order(sphx_graph *g, void *scratch, sphx_graph *out, int32_t **perm,
+                       int32_t **inv, hipStream_t s);
 
 // ------------------------------------------------------------------ spmm
 // Epilogue parameters.

@@ -414,6 +414,244 @@ __global__ void k_fill_int(int *x, int cnt, int v) {
 
 }  // namespace
 
+namespace {
+
+// ---- degree order: rows by floor(log2 degree), descending, ties in
+// increasing id (a stable bucket sort), so that the frequently gathered rows
+// of high degree share cache lines
+constexpr int kOrdCls = 32;
+constexpr int kOrdRows = 1024;   // rows per counting block
+
+template <typename IdxT>
+__device__ __forceinline__ int ord_class(const IdxT *rp, int64_t i) {
+  const int64_t d = (int64_t)rp[i + 1] - (int64_t)rp[i];
+  int lg = 0;
+  for (int64_t x = d; x > 1; x >>= 1) ++lg;
+  return kOrdCls - 1 - min(lg, kOrdCls - 1);
+}
+
+template <typename IdxT>
+__global__ __launch_bounds__(256) void k_ord_count(int64_t n, const IdxT *rp, int *counts) {
+  __shared__ int c[kOrdCls];
+  if (threadIdx.x < kOrdCls) c[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * kOrdRows;
+  for (int t = threadIdx.x; t < kOrdRows; t += blockDim.x) {
+    const int64_t i = r0 + t;
+    if (i < n) atomicAdd(&c[ord_class(rp, i)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrdCls) counts[blockIdx.x * kOrdCls + threadIdx.x] = c[threadIdx.x];
+}
+
+// counts[b][c] -> start of block b's class-c rows in the new order (class 0
+// first): one thread per class scans the blocks, then thread 0 adds the
+// class offsets
+__global__ __launch_bounds__(64) void k_ord_scan(int nblocks, int *counts) {
+  __shared__ long long tot[kOrdCls];
+  const int c = threadIdx.x;
+  if (c < kOrdCls) {
+    long long acc = 0;
+    for (int b = 0; b < nblocks; ++b) {
+      const int v = counts[b * kOrdCls + c];
+      counts[b * kOrdCls + c] = (int)acc;
+      acc += v;
+    }
+    tot[c] = acc;
+  }
+  __syncthreads();
+  if (c < kOrdCls) {
+    long long base = 0;
+    for (int q = 0; q < c; ++q) base += tot[q];
+    for (int b = 0; b < nblocks; ++b) counts[b * kOrdCls + c] += (int)base;
+  }
+}
+
+// perm[new] = old
+template <typename IdxT>
+__global__ __launch_bounds__(256) void k_ord_scatter(int64_t n, const IdxT *rp,
+                                                     const int *offsets, int32_t *perm) {
+  __shared__ int cnt[kOrdCls][256];
+  const int per = kOrdRows / 256;
+  const int64_t r0 = (int64_t)blockIdx.x * kOrdRows + (int64_t)threadIdx.x * per;
+  int local[kOrdCls];
+  for (int c = 0; c < kOrdCls; ++c) local[c] = 0;
+  for (int t = 0; t < per; ++t) {
+    const int64_t i = r0 + t;
+    if (i < n) local[ord_class(rp, i)]++;
+  }
+  for (int c = 0; c < kOrdCls; ++c) cnt[c][threadIdx.x] = local[c];
+  __syncthreads();
+  if (threadIdx.x < kOrdCls) {
+    const int c = threadIdx.x;
+    int acc = 0;
+    for (int t = 0; t < 256; ++t) {
+      const int v = cnt[c][t];
+      cnt[c][t] = acc;
+      acc += v;
+    }
+  }
+  __syncthreads();
+  int pos[kOrdCls];
+  for (int c = 0; c < kOrdCls; ++c)
+    pos[c] = offsets[blockIdx.x * kOrdCls + c] + cnt[c][threadIdx.x];
+  for (int t = 0; t < per; ++t) {
+    const int64_t i = r0 + t;
+    if (i < n) perm[pos[ord_class(rp, i)]++] = (int32_t)i;
+  }
+}
+
+template <typename IdxT>
+__global__ __launch_bounds__(256) void k_ord_degrees(int64_t n, const IdxT *rp,
+                                                     const int32_t *perm, int32_t *inv,
+                                                     long long *deg_new) {
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * 256) {
+    const int64_t o = perm[p];
+    inv[o] = (int32_t)p;
+    deg_new[p] = (long long)rp[o + 1] - (long long)rp[o];
+  }
+}
+
+// exclusive scan of deg_new into the new row pointers: block sums, a scan of
+// the block sums (one block), then each block's local scan plus its offset
+constexpr int kScanRows = 1024;
+
+__global__ __launch_bounds__(256) void k_scan_sums(int64_t n, const long long *x,
+                                                   long long *bsum) {
+  __shared__ long long sh[4];
+  const int64_t r0 = (int64_t)blockIdx.x * kScanRows;
+  long long acc = 0;
+  for (int t = threadIdx.x; t < kScanRows; t += 256) {
+    const int64_t i = r0 + t;
+    if (i < n) acc += x[i];
+  }
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ __launch_bounds__(64) void k_scan_bsums(int nb, long long *bsum) {
+  if (threadIdx.x == 0) {
+    long long acc = 0;
+    for (int b = 0; b < nb; ++b) {
+      const long long v = bsum[b];
+      bsum[b] = acc;
+      acc += v;
+    }
+  }
+}
+
+template <typename IdxT>
+__global__ __launch_bounds__(256) void k_scan_rows(int64_t n, const long long *x,
+                                                   const long long *bsum, IdxT *out) {
+  __shared__ long long sh[kScanRows];
+  const int64_t r0 = (int64_t)blockIdx.x * kScanRows;
+  for (int t = threadIdx.x; t < kScanRows; t += 256) {
+    const int64_t i = r0 + t;
+    sh[t] = i < n ? x[i] : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long acc = bsum[blockIdx.x];
+    for (int t = 0; t < kScanRows; ++t) {
+      const long long v = sh[t];
+      sh[t] = acc;
+      acc += v;
+    }
+    if (r0 + kScanRows >= n) out[n] = (IdxT)acc;   // the last block writes the total
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kScanRows; t += 256) {
+    const int64_t i = r0 + t;
+    if (i < n) out[i] = (IdxT)sh[t];
+  }
+}
+
+// new row p = old row perm[p], columns renamed by inv: one wavefront per row
+template <typename IdxT, typename WT>
+__global__ __launch_bounds__(256) void k_ord_rows(int64_t n, const IdxT *rp, const int32_t *col,
+                                                  const WT *w, const int32_t *perm,
+                                                  const int32_t *inv, const IdxT *rp_new,
+                                                  int32_t *col_new, WT *w_new) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t p = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6; p < n;
+       p += ((int64_t)gridDim.x * 256) >> 6) {
+    const int64_t o = perm[p];
+    const int64_t k0 = rp[o], d = (int64_t)rp[o + 1] - k0, q0 = rp_new[p];
+    for (int64_t k = lane; k < d; k += 64) {
+      col_new[q0 + k] = inv[col[k0 + k]];
+      if constexpr (!std::is_same_v<WT, Unit>) w_new[q0 + k] = w[k0 + k];
+    }
+  }
+}
+
+}  // namespace
+
+size_t degree_order_bytes(const sphx_graph *g) {
+  const int64_t n = g->n;
+  const int64_t nb = ceil_div(n, kOrdRows);
+  const size_t ib = g->rp64 ? 8 : 4;
+  const size_t wb = g->wdt == SPHX_F64 ? 8 : (g->wdt == SPHX_F32 ? 4 : 0);
+  size_t b = 0;
+  b += align_up(sizeof(int32_t) * n, 256) * 2;                 // perm, inv
+  b += align_up(ib * (n + 1), 256);                            // row pointers
+  b += align_up(sizeof(int32_t) * g->nnz, 256);                // columns
+  b += align_up(wb * g->nnz, 256);                             // weights
+  b += align_up(sizeof(long long) * n, 256);                   // new degrees
+  b += align_up(sizeof(int) * nb * kOrdCls, 256);              // class counts
+  b += align_up(sizeof(long long) * ceil_div(n, kScanRows), 256);
+  return b + 1024;
+}
+
+int build_degree_order(sphx_graph *g, void *scratch, sphx_graph *out, int32_t **perm_out,
+                       int32_t **inv_out, hipStream_t s) {
+  const int64_t n = g->n;
+  const int64_t nb = ceil_div(n, kOrdRows);
+  const size_t wb = g->wdt == SPHX_F64 ? 8 : (g->wdt == SPHX_F32 ? 4 : 0);
+  Arena a;
+  a.base = static_cast<char *>(scratch);
+  int32_t *perm = a.take<int32_t>(n);
+  int32_t *inv = a.take<int32_t>(n);
+  char *rpn = a.take<char>((g->rp64 ? 8 : 4) * (n + 1));
+  int32_t *coln = a.take<int32_t>(g->nnz);
+  char *wn = a.take<char>(wb * g->nnz);
+  long long *degn = a.take<long long>(n);
+  int *counts = a.take<int>(nb * kOrdCls);
+  long long *bsum = a.take<long long>(ceil_div(n, kScanRows));
+  const unsigned gs = (unsigned)ceil_div(n, kScanRows);
+  auto go = [&](auto idx_tag, auto w_tag) {
+    using IdxT = decltype(idx_tag);
+    using WT = decltype(w_tag);
+    const IdxT *rp = static_cast<const IdxT *>(g->rowptr);
+    hipLaunchKernelGGL((k_ord_count<IdxT>), dim3((unsigned)nb), dim3(256), 0, s, n, rp, counts);
+    hipLaunchKernelGGL(k_ord_scan, dim3(1), dim3(64), 0, s, (int)nb, counts);
+    hipLaunchKernelGGL((k_ord_scatter<IdxT>), dim3((unsigned)nb), dim3(256), 0, s, n, rp,
+                       (const int *)counts, perm);
+    hipLaunchKernelGGL((k_ord_degrees<IdxT>), dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n,
+                       rp, (const int32_t *)perm, inv, degn);
+    hipLaunchKernelGGL(k_scan_sums, dim3(gs), dim3(256), 0, s, n, (const long long *)degn, bsum);
+    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(64), 0, s, (int)gs, bsum);
+    hipLaunchKernelGGL((k_scan_rows<IdxT>), dim3(gs), dim3(256), 0, s, n,
+                       (const long long *)degn, (const long long *)bsum, (IdxT *)rpn);
+    hipLaunchKernelGGL((k_ord_rows<IdxT, WT>), dim3(grid_for(n, 4, 8192)), dim3(256), 0, s, n,
+                       rp, g->col, static_cast<const WT *>(g->w), (const int32_t *)perm,
+                       (const int32_t *)inv, (const IdxT *)rpn, coln, (WT *)wn);
+  };
+  with_types(g, go);
+  SPHX_HIP(g->h, hipGetLastError());
+  *out = *g;
+  out->rowptr = rpn;
+  out->col = coln;
+  out->w = wb ? wn : nullptr;
+  out->vwgt = nullptr;
+  out->stats_valid = 0;
+  *perm_out = perm;
+  *inv_out = inv;
+  return SPHX_OK;
+}
+
 // the int16 column offsets are kept for unit-weight graphs with 32-bit row
 // pointers that are (or may be, before their degrees are known) unbinned
 static bool may_compress(const sphx_graph *g) {

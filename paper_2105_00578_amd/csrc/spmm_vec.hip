@@ -468,12 +468,11 @@ void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X
     used += (int)gb;
   };
   if (!plan.binned) {
-    // rows of 13..48 neighbours: wide gathered rows (>= 32 bytes) amortise a
-    // lane's serial walk over the row: two lanes per row, one for FP64 rows
-    // of unit-weight graphs (FP32 keeps two, whose shorter per-lane sums
-    // round less); narrow rows take four lanes
+    // rows of 13..48 neighbours: wide gathered rows (>= 32 bytes) take two
+    // lanes per row (measured on the 27-point meshes against one and four
+    // lanes, FP32 and FP64), narrow rows four
     int G = plan.group;
-    if (G > 1 && VB * NV >= 32) G = (std::is_same_v<T, double> && kUnitW<WT>) ? 1 : 2;
+    if (G > 1 && VB * NV >= 32) G = 2;
     if (G == 1) short_rows(nullptr, n, kMaxShortBlocks);
     else grouped(G, nullptr, n, kGroupBlocks);
   } else {

@@ -207,3 +207,85 @@ def test_partition_after_promotion_splits_the_returned_vectors(handle):
     assert st.promoted == 1
     ref = split.split_mj(V.cpu().numpy()[:, 1:], 8)
     assert np.array_equal(part.cpu().numpy(), ref)
+
+
+# ---- degree order of graphs with rows above 48 neighbours
+
+def _hub_graph(wd, seed):
+    """A random graph plus two hubs of 300 and 120 neighbours (binned rows)."""
+    rng = np.random.default_rng(seed)
+    n = 900
+    iu, ju = np.triu_indices(n, 1)
+    keep = rng.random(iu.size) < 0.006
+    u = np.concatenate([iu[keep], np.arange(n - 1), np.zeros(300, int), np.full(120, 5)])
+    v = np.concatenate([ju[keep], np.arange(1, n), rng.choice(np.arange(1, n), 300, replace=False),
+                        rng.choice(np.arange(6, n), 120, replace=False)])
+    key = np.unique(np.minimum(u, v) * n + np.maximum(u, v))
+    u, v = key // n, key % n
+    w = None if wd is None else graphgen.uniform_weights(u.size, seed, dtype=wd)
+    return graphgen.csr_from_edges(n, u, v, w)
+
+
+@pytest.mark.parametrize("wd,rp64", [(None, False), (np.float64, True), (np.float32, False)])
+@pytest.mark.parametrize("problem", [sx.COMBINATORIAL, sx.GENERALIZED, sx.NORMALIZED])
+def test_degree_order_matches_dense_and_caller_order(handle, wd, rp64, problem):
+    g = _hub_graph(wd, 7)
+    assert np.diff(g.rowptr).max() > 48
+    rp, col, w = upload(g, rowptr64=rp64)
+    G = sx.Graph(handle, rp, col, w)
+    wo = None if g.w is None else g.w.astype(np.float64)
+    nev = 4
+    if problem == sx.NORMALIZED:
+        L = lap.dense_normalized(g.rowptr, g.col, wo)
+        bd = np.ones(g.n)
+    else:
+        L, d = lap.dense(g.rowptr, g.col, wo)
+        bd = d if problem == sx.GENERALIZED else np.ones(g.n)
+    lam_ref, V_ref = eigen.smallest_dense(L, bd, nev + 1)
+    res = {}
+    for ro in (1, 0):
+        opts = sx.Options(problem=problem, precond=sx.PRECOND_JACOBI, tol=1e-9,
+                          precision=sx.FP64, seed=3, max_iter=5000, reorder=ro)
+        lam, V, st = sx.eigensolve(handle, G, nev, opts)
+        Vh = V.cpu().numpy()
+        assert abs(lam[0]) <= 1e-6 * lam_ref[1]
+        assert np.allclose(lam[1:], lam_ref[1:nev], rtol=1e-6, atol=0)
+        assert np.allclose(Vh.T @ (bd[:, None] * Vh), np.eye(nev), atol=1e-9)
+        gap = lam_ref[nev] - lam_ref[nev - 1]
+        if np.sqrt(nev) * 1e-9 * lam_ref[nev - 1] / gap < 1e-4:
+            assert eigen.subspace_sin(Vh, V_ref[:, :nev], bd) < 1e-3
+        # sign rule on the caller's order: the largest-magnitude entry is positive
+        for k in range(nev):
+            assert Vh[int(np.argmax(np.abs(Vh[:, k]))), k] > 0
+        res[ro] = lam
+    assert np.allclose(res[0][1:], res[1][1:], rtol=1e-7)
+
+
+def test_degree_order_user_start_and_gmres(handle):
+    g = _hub_graph(None, 9)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    opts = sx.Options(precond=sx.PRECOND_GMRES, cheb_degree=10, tol=1e-9, precision=sx.FP64,
+                      seed=4, max_iter=2000)
+    lam, V, st = sx.eigensolve(handle, G, 4, opts)
+    L, _ = lap.dense(g.rowptr, g.col, None)
+    lam_ref, _ = eigen.smallest_dense(L, np.ones(g.n), 5)
+    assert np.allclose(lam[1:], lam_ref[1:4], rtol=1e-6)
+    # the converged vectors, given back in the caller's order, restart converged
+    opts.init = sx.INIT_USER
+    lam2, V2, st2 = sx.eigensolve(handle, G, 4, opts, X0=V)
+    assert st2.iterations <= 2
+    assert np.allclose(lam2, lam, rtol=1e-9, atol=1e-12)
+
+
+def test_degree_order_partition_split(handle):
+    from oracle import split, quality
+    g = graphgen.rmat_graph(12, seed=5)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    reg, _, _ = G.info()
+    opts = sx.options_default(reg, sx.PRECOND_CHEBYSHEV, precision=sx.MIXED, seed=2)
+    lam, V, part, cut, imb, st = sx.partition(handle, G, 16, opts)
+    ref = split.split_mj(V.cpu().numpy()[:, 1:], 16)
+    assert np.array_equal(part.cpu().numpy(), ref)
+    assert cut == quality.cutsize(g.rowptr, g.col, None, ref)[0]

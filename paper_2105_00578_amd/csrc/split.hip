@@ -79,18 +79,22 @@ __device__ __forceinline__ bool prefix_match(K ord, uint32_t id, K pord, uint32_
   return (id & mask) == pid;
 }
 
-constexpr int kLdsTargets = 16;
+// Up to 32 targets count in LDS first (16 or 32 rows of 256 bins), more in
+// global memory.
+constexpr int kLdsTargets = 32;
 
 // Histogram of byte d over the members of every target's section whose first
 // d key bytes match the target's prefix.  Target t = s * (p - 1) + j - 1.
-template <typename K, bool kLds>
+// LT: targets held in LDS (0: global atomics).
+template <typename K, int LT>
 __global__ __launch_bounds__(256) void k_hist(int64_t n, const K *__restrict__ keys,
                                               const int32_t *__restrict__ part,
                                               const int32_t *__restrict__ vwgt, int d, int p,
                                               int ntgt, const K *__restrict__ pord,
                                               const uint32_t *__restrict__ pid,
                                               unsigned long long *hist) {
-  __shared__ unsigned long long h[kLds ? kLdsTargets * 256 : 1];
+  constexpr bool kLds = LT > 0;
+  __shared__ unsigned long long h[kLds ? LT * 256 : 1];
   if constexpr (kLds) {
     for (int e = threadIdx.x; e < ntgt * 256; e += blockDim.x) h[e] = 0;
     __syncthreads();
@@ -117,33 +121,61 @@ __global__ __launch_bounds__(256) void k_hist(int64_t n, const K *__restrict__ k
   }
 }
 
-// One thread per target: choose byte d (the first bucket where p * C reaches
-// j * W), clear the histogram row.
+// One wavefront per target: choose byte d (the first bucket where p * C
+// reaches j * W), clear the histogram row.  Lane l holds buckets 4l .. 4l+3;
+// the weight before a lane's buckets is an exclusive scan over the lanes, and
+// the lowest lane with a qualifying bucket holds the choice.
 template <typename K>
-__global__ void k_select(int ntgt, int p, int d, int nd, unsigned long long *hist, K *pord,
-                         uint32_t *pid, long long *base, const long long *W,
-                         long long *wstar) {
+__global__ __launch_bounds__(256) void k_select(int ntgt, int p, int d, int nd,
+                                                unsigned long long *hist, K *pord,
+                                                uint32_t *pid, long long *base,
+                                                const long long *W, long long *wstar) {
   constexpr int OB = sizeof(K);
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntgt) return;
+  const int lane = threadIdx.x & 63;
+  const int t = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (t >= ntgt) return;   // wave-uniform
   const int s = t / (p - 1);
   const long long jW = (long long)(t % (p - 1) + 1) * W[s];
-  long long cum = base[t];
-  int chosen = -1;
-  long long hb = 0;
-  for (int b = 0; b < 256; ++b) {
-    long long v = (long long)hist[(int64_t)t * 256 + b];
-    hist[(int64_t)t * 256 + b] = 0;
-    if (chosen < 0) {
-      if (v > 0 && (long long)p * (cum + v) >= jW) { chosen = b; hb = v; }
-      else cum += v;
+  unsigned long long *row = hist + (int64_t)t * 256 + 4 * lane;
+  long long v[4], local = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    v[u] = (long long)row[u];
+    row[u] = 0;
+    local += v[u];
+  }
+  long long incl = local;
+  for (int off = 1; off < 64; off <<= 1) {
+    const long long y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  long long cum = base[t] + (incl - local);
+  int pick = -1;
+  long long hb = 0, at = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (pick < 0) {
+      if (v[u] > 0 && (long long)p * (cum + v[u]) >= jW) {
+        pick = 4 * lane + u;
+        hb = v[u];
+        at = cum;
+      } else {
+        cum += v[u];
+      }
     }
   }
-  if (chosen < 0) return;   // empty section
-  base[t] = cum;
-  if (d < OB) pord[t] |= (K)chosen << (8 * (OB - 1 - d));
-  else pid[t] |= (uint32_t)chosen << (8 * (3 - (d - OB)));
-  if (d == nd - 1) wstar[t] = hb;
+  const unsigned long long mask = __ballot(pick >= 0);
+  if (mask == 0ull) return;   // empty section
+  const int first = __ffsll((long long)mask) - 1;
+  const int chosen = __shfl(pick, first);
+  hb = __shfl(hb, first);
+  at = __shfl(at, first);
+  if (lane == 0) {
+    base[t] = at;
+    if (d < OB) pord[t] |= (K)chosen << (8 * (OB - 1 - d));
+    else pid[t] |= (uint32_t)chosen << (8 * (3 - (d - OB)));
+    if (d == nd - 1) wstar[t] = hb;
+  }
 }
 
 // Per target: include e* or not; lo[t] = weight of the prefix before the cut.
@@ -276,16 +308,20 @@ int split_mj(sphx_graph *g, const T *coords, int ld, int ncoord, int K, int32_t 
     const int ntgt = nsec * (p - 1);
     const int c = (int)(l % (size_t)ncoord);
     const unsigned gt = grid_for(ntgt, 256, 1 << 16);
+    const unsigned gw = (unsigned)ceil_div(ntgt, 4);   // one wavefront per target
     hipLaunchKernelGGL((k_keys<T>), dim3(gn), dim3(256), 0, s, coords, ld, c, n, keys, flag);
     hipLaunchKernelGGL((k_reset<KT>), dim3(gt), dim3(256), 0, s, ntgt, pord, pid, base);
     for (int d = 0; d < nd; ++d) {
-      if (ntgt <= kLdsTargets)
-        hipLaunchKernelGGL((k_hist<KT, true>), dim3(gn), dim3(256), 0, s, n, keys, part,
+      if (ntgt <= 16)
+        hipLaunchKernelGGL((k_hist<KT, 16>), dim3(gn), dim3(256), 0, s, n, keys, part,
+                           g->vwgt, d, p, ntgt, pord, pid, hist);
+      else if (ntgt <= kLdsTargets)
+        hipLaunchKernelGGL((k_hist<KT, kLdsTargets>), dim3(gn), dim3(256), 0, s, n, keys, part,
                            g->vwgt, d, p, ntgt, pord, pid, hist);
       else
-        hipLaunchKernelGGL((k_hist<KT, false>), dim3(gn), dim3(256), 0, s, n, keys, part,
+        hipLaunchKernelGGL((k_hist<KT, 0>), dim3(gn), dim3(256), 0, s, n, keys, part,
                            g->vwgt, d, p, ntgt, pord, pid, hist);
-      hipLaunchKernelGGL((k_select<KT>), dim3(gt), dim3(256), 0, s, ntgt, p, d, nd, hist, pord,
+      hipLaunchKernelGGL((k_select<KT>), dim3(gw), dim3(256), 0, s, ntgt, p, d, nd, hist, pord,
                          pid, base, W, wstar);
     }
     hipLaunchKernelGGL(k_finish_targets, dim3(gt), dim3(256), 0, s, ntgt, p, base, W, wstar,

@@ -54,7 +54,6 @@ def closed_form_check(lam, V, side):
     spectrum of the side^3 grid (sums of path eigenvalues, tensor vectors)."""
     import numpy as np
     from tests import closed_forms as cf
-    from oracle import eigen
     m = len(lam)
     exact = cf.grid_eigvals((side, side, side), m + 1)
     rel = [abs(lam[k] - exact[k]) / exact[k] for k in range(1, m)]
@@ -68,7 +67,11 @@ def closed_form_check(lam, V, side):
     val = {k: sum(cf.path_eigval(side, q) for q in k) for k in ks}
     ks = sorted(ks, key=lambda k: val[k])[:m]
     E = np.stack([cf.grid_eigvec((side, side, side), k) for k in ks], axis=1)
-    sin = eigen.subspace_sin(V.astype(np.float64), E, np.ones(V.shape[0]))
+    # sine of the largest principal angle between span(V) and span(E)
+    qv, _ = np.linalg.qr(V.astype(np.float64))
+    qe, _ = np.linalg.qr(E)
+    smin = np.linalg.svd(qv.T @ qe, compute_uv=False).min()
+    sin = float(np.sqrt(max(0.0, 1.0 - smin * smin)))
     return max(rel), trivial, sin, float(exact[m] - exact[m - 1])
 
 

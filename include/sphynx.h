@@ -177,12 +177,14 @@ int sphx_set_timing(sphx_handle *h, int on);
 /* Eq. 4: number of eigenvectors d = floor(log2 K) + 1 (K >= 1), else -1. */
 int sphx_num_eigenvectors(int K);
 
-/* Defaults of Sec. 6.3.1 ("Sphynx Default Settings") for a preconditioner:
- * regular graphs use the combinatorial problem; irregular graphs the
- * normalized one with a polynomial (Chebyshev or GMRES) preconditioner and
- * the generalized one otherwise; the tolerance is 1e-3 on regular graphs and 1e-2
- * on irregular ones; initial vectors are random on regular graphs and
- * piecewise constant on irregular ones (Sec. 6.2.1). */
+/* Defaults of Sec. 6.3.1 for a preconditioner: regular graphs use the
+ * combinatorial problem; irregular graphs the normalized one with a
+ * polynomial (Chebyshev or GMRES) preconditioner and the generalized one
+ * otherwise; the tolerance is 1e-3 on regular graphs and 1e-2 on irregular
+ * ones; initial vectors are random on regular graphs and piecewise constant
+ * on irregular ones (Sec. 6.2.1).  The other fields: degree 25, ratio 1000,
+ * FP64, max_iter 10000, locking on, drop_tol 0 (automatic),
+ * promote_window 0 (100 iterations), reorder 1. */
 void sphx_options_default(sphx_options *opt, int graph_is_regular, int precond);
 
 /* ---------------------------------------------------------------- graphs */

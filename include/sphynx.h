@@ -112,8 +112,8 @@ typedef struct sphx_options {
                              below 0.7 of its value at the last such
                              progress, the iteration continues in FP64 from
                              the current vectors (stats.promoted = 1; the
-                             returned vectors stay FP32).  0 = 100,
-                             < 0 = never.                                     */
+                             returned vectors stay FP32; max_iter bounds
+                             both parts together).  0 = 100, < 0 = never.    */
     int reorder;          /* 1 (default): graphs with rows of more than 48
                              neighbours are solved on a copy whose rows are
                              ordered by floor(log2 degree), descending (ties

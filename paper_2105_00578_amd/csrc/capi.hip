@@ -441,7 +441,7 @@ int poly_apply(sphx_handle *h, sphx_graph *g, const SpmmPlan &plan, int m, int l
 template <typename T>
 int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const void *X0,
           double *eigvals, T *vecs_out, sphx_stats *stats, SolveWs<T> &w, char *wsbase,
-          bool *hit_max, bool *stalled) {
+          bool *hit_max, bool *stalled, int *iterations) {
   hipStream_t s = h->stream;
   const int64_t n = g->n;
   int64_t calls = 0, pcalls = 0, pcols = 0;
@@ -646,6 +646,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     }
   }
   *hit_max = hs->nact > 0 && !(stalled && *stalled);
+  if (iterations) *iterations = it;
   // ---- final FP64 residual check and normalisation
   double *X64 = reinterpret_cast<double *>(w.X);
   double *LX64 = reinterpret_cast<double *>(w.LX);
@@ -1227,7 +1228,9 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
     T *vecs = eigvecs ? static_cast<T *>(eigvecs) : w.V;
     if (!vecs) return set_err(h, SPHX_E_INVALID_ARG, "eigvecs is NULL");
     bool stalled = false;
-    SPHX_TRY(solve<T>(h, g, nev, *o, X0, eigvals, vecs, stats, w, ws, &hit_max, &stalled));
+    int its = 0;
+    SPHX_TRY(solve<T>(h, g, nev, *o, X0, eigvals, vecs, stats, w, ws, &hit_max, &stalled,
+                      &its));
     if constexpr (std::is_same_v<T, float>) {
       if (stalled) {
         // continue in FP64 from the current vectors (their normalised form,
@@ -1244,10 +1247,11 @@ static int eigensolve_impl(sphx_handle *h, sphx_graph *g, int nev, const sphx_op
         o64.precision = SPHX_FP64;
         o64.init = SPHX_INIT_USER;
         o64.drop_tol = 0.0;
+        o64.max_iter = std::max(1, o->max_iter - its);   // one budget for both parts
         sphx_stats s64;
         std::memset(&s64, 0, sizeof(s64));
         SPHX_TRY(solve<double>(h, g, nev, o64, x0, eigvals, v64, stats ? &s64 : nullptr, w64,
-                               (char *)a64.base, &hit_max, nullptr));
+                               (char *)a64.base, &hit_max, nullptr, nullptr));
         launch_convert<double, float>(v64, vecs, (int64_t)g->n * nev, h->stream);
         if (stats) {
           stats->iterations += s64.iterations;

@@ -289,3 +289,13 @@ def test_degree_order_partition_split(handle):
     ref = split.split_mj(V.cpu().numpy()[:, 1:], 16)
     assert np.array_equal(part.cpu().numpy(), ref)
     assert cut == quality.cutsize(g.rowptr, g.col, None, ref)[0]
+
+
+def test_mixed_promotion_shares_the_iteration_budget(handle):
+    g = random_graph(400, 0.015, 21, np.float32)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    opts = sx.Options(problem=sx.GENERALIZED, precond=sx.PRECOND_JACOBI, tol=1e-12,
+                      precision=sx.MIXED, seed=3, max_iter=60, promote_window=10)
+    lam, V, st = sx.eigensolve(handle, G, 4, opts, allow_not_converged=True)
+    assert st.promoted == 1 and st.iterations <= 60

@@ -256,7 +256,13 @@ constexpr int LDA = kMaxW + 1;
 static_assert(kMaxW < 64, "Rayleigh-Ritz pivot search: one candidate per lane of a wave");
 
 // Cyclic Jacobi eigensolver (round-robin parallel ordering) on the k x k
-// symmetric matrix A (LDS, stride LDA); V receives the eigenvectors.
+// symmetric matrix A (LDS, stride LDA); V receives the eigenvectors.  The
+// pairs of one round are disjoint, so A <- R^T A R splits into independent
+// 2 x 2 blocks (pair I's rows, pair J's columns): each thread takes one block,
+// rotates its rows with pair I's angle, then its columns with pair J's (the
+// same operations, in the same order, as a row pass followed by a column
+// pass), and V <- V R likewise by blocks.  One barrier after the angles and
+// one after the update per round.
 __device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
                            int *pp, int *pq, int *changed) {
   __shared__ double anorm;
@@ -265,11 +271,14 @@ __device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
     int i = e / k, j = e - i * k;
     V[i * LDA + j] = (i == j) ? 1.0 : 0.0;
   }
-  if (t == 0) {
+  if (t < 64) {
     double s = 0.0;
-    for (int i = 0; i < k; ++i)
-      for (int j = 0; j < k; ++j) s += A[i * LDA + j] * A[i * LDA + j];
-    anorm = sqrt(s);
+    for (int e = t; e < k * k; e += 64) {
+      int i = e / k, j = e - i * k;
+      s += A[i * LDA + j] * A[i * LDA + j];
+    }
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (t == 0) anorm = sqrt(s);
   }
   __syncthreads();
   if (k < 2) return;
@@ -278,6 +287,7 @@ __device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
   const double abs_floor = 4e-16 * anorm + 1e-300;
   const int kk = k + (k & 1);
   const int npair = kk / 2;
+  const int nblk = npair * npair;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (t == 0) *changed = 0;
     __syncthreads();
@@ -302,31 +312,37 @@ __device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
         pp[t] = p; pq[t] = q; pc[t] = c; ps[t] = s;
       }
       __syncthreads();
-      // rows: A <- R^T A
-      for (int e = t; e < npair * k; e += blockDim.x) {
-        int i = e / k, j = e - i * k;
-        double s = ps[i];
-        if (s == 0.0) continue;
-        double c = pc[i];
-        int p = pp[i], q = pq[i];
-        double ap = A[p * LDA + j], aq = A[q * LDA + j];
-        A[p * LDA + j] = c * ap - s * aq;
-        A[q * LDA + j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      // columns: A <- A R, V <- V R
-      for (int e = t; e < npair * k; e += blockDim.x) {
-        int i = e / k, j = e - i * k;
-        double s = ps[i];
-        if (s == 0.0) continue;
-        double c = pc[i];
-        int p = pp[i], q = pq[i];
-        double ap = A[j * LDA + p], aq = A[j * LDA + q];
-        A[j * LDA + p] = c * ap - s * aq;
-        A[j * LDA + q] = s * ap + c * aq;
-        double vp = V[j * LDA + p], vq = V[j * LDA + q];
-        V[j * LDA + p] = c * vp - s * vq;
-        V[j * LDA + q] = s * vp + c * vq;
+      // blocks of A (e < nblk) and of V (nblk <= e < 2 nblk); a pair whose
+      // second index is k (odd k) has no rotation and only its first row
+      for (int e = t; e < 2 * nblk; e += blockDim.x) {
+        const bool isv = e >= nblk;
+        const int b = isv ? e - nblk : e;
+        const int I = b / npair, J = b - I * npair;
+        const double sI = isv ? 0.0 : ps[I], sJ = ps[J];
+        if (sI == 0.0 && sJ == 0.0) continue;
+        double *M = isv ? V : A;
+        const int p0 = pp[I], q0 = pq[I], p1 = pp[J], q1 = pq[J];
+        const bool r1 = q0 < k, c1 = q1 < k;
+        double a00 = M[p0 * LDA + p1];
+        double a01 = c1 ? M[p0 * LDA + q1] : 0.0;
+        double a10 = r1 ? M[q0 * LDA + p1] : 0.0;
+        double a11 = (r1 && c1) ? M[q0 * LDA + q1] : 0.0;
+        if (sI != 0.0) {
+          const double cI = pc[I];
+          const double b00 = cI * a00 - sI * a10, b10 = sI * a00 + cI * a10;
+          const double b01 = cI * a01 - sI * a11, b11 = sI * a01 + cI * a11;
+          a00 = b00; a10 = b10; a01 = b01; a11 = b11;
+        }
+        if (sJ != 0.0) {
+          const double cJ = pc[J];
+          const double b00 = cJ * a00 - sJ * a01, b01 = sJ * a00 + cJ * a01;
+          const double b10 = cJ * a10 - sJ * a11, b11 = sJ * a10 + cJ * a11;
+          a00 = b00; a01 = b01; a10 = b10; a11 = b11;
+        }
+        M[p0 * LDA + p1] = a00;
+        if (c1) M[p0 * LDA + q1] = a01;
+        if (r1) M[q0 * LDA + p1] = a10;
+        if (r1 && c1) M[q0 * LDA + q1] = a11;
       }
       __syncthreads();
     }

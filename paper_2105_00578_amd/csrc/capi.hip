@@ -556,7 +556,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   UpdateArgs ua{n, m, ld, idm, 0, 0};
   ua.act.count = 0;
   tid = pl.begin(PH_UPDATE, 0.0, s);
-  launch_update<T>(w.X, nullptr, w.P, nullptr, w.LP, w.Y, ua, s);
+  SPHX_TRY(launch_update<T>(w.X, nullptr, w.P, nullptr, w.LP, w.Y, ua, s));
   pl.end(tid, s);
   const bool jac = o.precond == SPHX_PRECOND_JACOBI;
   auto residual = [&]() -> int {
@@ -622,7 +622,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     pl.end(tid, s);
     UpdateArgs ub{n, m, ld, act, 1, have_p ? 1 : 0};
     tid = pl.begin(PH_UPDATE, 0.0, s);
-    launch_update<T>(w.X, H, w.P, w.LH, w.LP, w.Y, ub, s);
+    SPHX_TRY(launch_update<T>(w.X, H, w.P, w.LH, w.LP, w.Y, ub, s));
     pl.end(tid, s);
     have_p = true;
     // Jacobi writes the next H into B1, which held this iteration's H (consumed

@@ -637,53 +637,87 @@ struct UpdDev {
   int offH, offP;     // rows of Y for the H and P parts
 };
 
-// Rows of all blocks have stride ld; thread t works on column t % ld of row
-// t / ld of a 256 / ld row chunk staged in LDS (padding columns untouched).
+// Rows of all blocks have stride ld, a multiple of E (4 floats: 16-byte
+// loads; FP64 elements are loaded one by one, which measured faster than
+// pairs).  A chunk of 256 E elements (256 E / ld rows) of each block is read
+// with one load per thread and block into LDS (kept in T; widened to double
+// where used); thread t then computes the elements t + 256 j of the chunk
+// (column c = e % ld < m; padding columns untouched), each as a sum in a
+// fixed order: the X part over k, plus the H and P parts over the active
+// columns.
+template <typename T> struct UpdVec;
+template <> struct UpdVec<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int E = 4;
+};
+template <> struct UpdVec<double> {
+  typedef double type;
+  static constexpr int E = 1;
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(T *X, const T *__restrict__ H, T *P,
                                                 const T *__restrict__ LH, T *LP,
                                                 const double *__restrict__ Yg, UpdDev a) {
+  using V = typename UpdVec<T>::type;
+  constexpr int E = UpdVec<T>::E;
+  constexpr int CH = 256 * E;
   __shared__ double sY[kMaxW * kMaxNev];
-  __shared__ double sX[256], sH[256], sP[256], sLH[256], sLP[256];
+  __shared__ V sX[256], sH[256], sP[256], sLH[256], sLP[256];
+  const T *lX = reinterpret_cast<const T *>(sX);
+  const T *lH = reinterpret_cast<const T *>(sH);
+  const T *lP = reinterpret_cast<const T *>(sP);
+  const T *lLH = reinterpret_cast<const T *>(sLH);
+  const T *lLP = reinterpret_cast<const T *>(sLP);
   const int m = a.m, ld = a.ld;
-  const int rc = 256 / ld;      // rows per chunk
+  const int rc = CH / ld;       // rows per chunk
   const int t = threadIdx.x;
   for (int e = t; e < kMaxW * kMaxNev; e += blockDim.x) sY[e] = Yg[e];
-  const int row = t / ld;
-  const int c = t - row * ld;
-  const bool live = row < rc && c < m;
   const bool write_p = a.use_h || a.use_p;
   for (int64_t r0 = (int64_t)blockIdx.x * rc; r0 < a.n; r0 += (int64_t)gridDim.x * rc) {
     const int64_t base = r0 * ld;
-    const int64_t lim = min((int64_t)rc, a.n - r0) * ld;
+    const int lim = (int)min((int64_t)rc, a.n - r0) * ld;
     __syncthreads();
-    if (t < lim) {
-      sX[t] = double(X[base + t]);
-      if (a.use_h) { sH[t] = double(H[base + t]); sLH[t] = double(LH[base + t]); }
-      if (a.use_p) { sP[t] = double(P[base + t]); sLP[t] = double(LP[base + t]); }
+    if (t * E < lim) {
+      const int64_t vb = base / E + t;
+      sX[t] = reinterpret_cast<const V *>(X)[vb];
+      if (a.use_h) {
+        sH[t] = reinterpret_cast<const V *>(H)[vb];
+        sLH[t] = reinterpret_cast<const V *>(LH)[vb];
+      }
+      if (a.use_p) {
+        sP[t] = reinterpret_cast<const V *>(P)[vb];
+        sLP[t] = reinterpret_cast<const V *>(LP)[vb];
+      }
     }
     __syncthreads();
-    if (live && t < lim) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int e = t + 256 * j;
+      if (e >= lim) break;
+      const int row = e / ld;
+      const int c = e - row * ld;
+      if (c >= m) continue;
       double p = 0.0, lp = 0.0, x = 0.0;
       const int o = row * ld;
       if (a.use_h)
         for (int q = 0; q < a.na; ++q) {
           double y = sY[(a.offH + q) * kMaxNev + c];
-          p += sH[o + a.act[q]] * y;
-          lp += sLH[o + a.act[q]] * y;
+          p += double(lH[o + a.act[q]]) * y;
+          lp += double(lLH[o + a.act[q]]) * y;
         }
       if (a.use_p)
         for (int q = 0; q < a.na; ++q) {
           double y = sY[(a.offP + q) * kMaxNev + c];
-          p += sP[o + a.act[q]] * y;
-          lp += sLP[o + a.act[q]] * y;
+          p += double(lP[o + a.act[q]]) * y;
+          lp += double(lLP[o + a.act[q]]) * y;
         }
-      for (int k = 0; k < m; ++k) x += sX[o + k] * sY[k * kMaxNev + c];
+      for (int k = 0; k < m; ++k) x += double(lX[o + k]) * sY[k * kMaxNev + c];
       x += p;
-      X[base + t] = T(x);
+      X[base + e] = T(x);
       if (write_p) {
-        P[base + t] = T(p);
-        LP[base + t] = T(lp);
+        P[base + e] = T(p);
+        LP[base + e] = T(lp);
       }
     }
   }
@@ -970,8 +1004,8 @@ void launch_rr(const double *gram_out, const RRArgs &a, double *Y, double *theta
 }
 
 template <typename T>
-void launch_update(T *X, const T *H, T *P, const T *LH, T *LP, const double *Y,
-                   const UpdateArgs &a, hipStream_t s) {
+int launch_update(T *X, const T *H, T *P, const T *LH, T *LP, const double *Y,
+                  const UpdateArgs &a, hipStream_t s) {
   UpdDev d;
   d.n = a.n;
   d.m = a.m;
@@ -982,9 +1016,13 @@ void launch_update(T *X, const T *H, T *P, const T *LH, T *LP, const double *Y,
   d.use_p = a.use_p && d.na > 0;
   d.offH = a.m;
   d.offP = a.m + (d.use_h ? d.na : 0);
-  int rc = 256 / a.ld;
+  // rows of whole load vectors (the solver pads every block to 16 bytes)
+  constexpr int E = UpdVec<T>::E;
+  if (a.ld % E != 0 || a.ld > 256 || a.m > a.ld) return SPHX_E_INVALID_ARG;
+  int rc = 256 * E / a.ld;
   hipLaunchKernelGGL((k_update<T>), dim3(grid_for(a.n, rc, 8192)), dim3(256), 0, s, X, H, P,
                      LH, LP, Y, d);
+  return hipGetLastError() == hipSuccess ? SPHX_OK : SPHX_E_HIP;
 }
 
 void launch_finalize(const double *norm_partials, int n_blocks, int m, const double *theta,
@@ -1050,7 +1088,7 @@ void launch_copy_cols(const T *in, int ldin, T *out, int ldout, int64_t n, int m
   template void launch_init_piecewise<T>(T *, int64_t, int, int, hipStream_t);             \
   template int gram<T>(const T *, const T *, const T *, const T *, const T *, const T *,   \
                        const GramArgs &, double *, int, double *, hipStream_t);            \
-  template void launch_update<T>(T *, const T *, T *, const T *, T *, const double *,      \
+  template int launch_update<T>(T *, const T *, T *, const T *, T *, const double *,      \
                                  const UpdateArgs &, hipStream_t);                         \
   template void launch_rq_partials<T>(const T *, const double *, int64_t, int, int,        \
                                       const double *, double *, int, hipStream_t);         \

@@ -201,9 +201,11 @@ struct UpdateArgs {
   ColMap act;
   int use_h, use_p;
 };
+// SPHX_E_INVALID_ARG unless ld is at most 256, at least m and, for FP32, a
+// multiple of 4.
 template <typename T>
-void launch_update(T *X, const T *H, T *P, const T *LH, T *LP, const double *Y,
-                   const UpdateArgs &a, hipStream_t s);
+int launch_update(T *X, const T *H, T *P, const T *LH, T *LP, const double *Y,
+                  const UpdateArgs &a, hipStream_t s);
 
 // Reduce norm partials -> rho, convergence, active list (one workgroup).
 void launch_finalize(const double *norm_partials, int n_blocks, int m,

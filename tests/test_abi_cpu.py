@@ -59,3 +59,15 @@ def test_create_without_gpu_fails_cleanly(lib):
     h = ctypes.c_void_p()
     lib.sphx_create.restype = ctypes.c_int
     assert lib.sphx_create(ctypes.byref(h), 0, None) < 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with status 2
+    and a message, before any device work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "4"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stdout + r.stderr

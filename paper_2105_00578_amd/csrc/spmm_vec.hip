@@ -153,6 +153,8 @@ struct VResidual {
                       double *n2) const {
     const double di = p.d64 ? p.d64[i] : 1.0;
     const double b = p.generalized ? di : 1.0;
+    // one division per row for the B^-1-norm terms (exactly 1 when B = I)
+    const double ib = p.generalized ? 1.0 / di : 1.0;
     V *lx = reinterpret_cast<V *>(p.LX + i * p.ld);
     V *out = reinterpret_cast<V *>(p.OUT + i * p.ld);
 #pragma unroll
@@ -166,7 +168,7 @@ struct VResidual {
         const double r = double(acc[v][e]) - b * th * x;
         o[e] = T(p.jacobi ? r / di : r);
         if (c < m) {
-          n1[c] += r * r / b;
+          n1[c] += r * r * ib;
           n2[c] += b * x * x;
         }
       }

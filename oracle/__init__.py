@@ -23,9 +23,14 @@ Modules
                weights (dense full-basis reference and projected solve)
   refine     - greedy refinement of a K-way partition under the balance
                constraint (Sec. 7, Sec. 3.1)
+  certify    - the d smallest eigenpairs of large graphs with error bounds
+               (Algorithm 1 far past the solver's tolerance, guard vectors,
+               quadratic residual and Davis-Kahan bounds)
+  csrc/      - the oracle's Laplacian product as a plain C/OpenMP loop
+               (built into liboracle.so with gcc; loaded by `_native`)
 
 Pins: every function is checked in tests/test_oracle_*.py against closed forms,
 library special cases, invariants or brute force.  No function here is
 "parity unpinned".
 """
-from . import laplacian, eigen, precond, split, quality, adjoint, refine  # noqa: F401
+from . import laplacian, eigen, precond, split, quality, adjoint, refine, certify  # noqa: F401

@@ -79,18 +79,23 @@ def rayleigh_ritz(S, LS, bd, nev, drop=1e-12):
 
 
 def lobpcg(rowptr, col, w, problem, X0, precond, tol, maxiter=10000,
-           locking=True):
+           locking=True, op=None, bd=None):
     """Algorithm 1 (LOBPCG, Hetmaniuk-Lehoucq form) for L x = lambda B x
     (L = L_N and B = I for the normalized problem).
 
     precond: callable R -> H (the solve "M H = R"), or None for H = R.
-    tol: bound on the relative residual rho_i of `laplacian.residual_norms`.
+    tol: bound on the relative residual rho_i of `laplacian.residual_norms`
+    (a scalar, or one bound per column).
     locking: soft locking -- only unconverged columns contribute residual
     directions and conjugate directions (the "I" subsets of Algorithm 1).
+    op, bd: the operator Z -> L Z and the diagonal of B, when the caller has
+    them already (large graphs: `laplacian.operator(..., fast=True)`).
     Returns (theta, X, iterations, rho).
     """
-    bd = laplacian.bdiag(rowptr, col, w, problem)
-    L = laplacian.operator(rowptr, col, w, problem)
+    if bd is None:
+        bd = laplacian.bdiag(rowptr, col, w, problem)
+    L = laplacian.operator(rowptr, col, w, problem) if op is None else op
+    tol = np.asarray(tol, dtype=np.float64)
     X = np.asarray(X0, dtype=np.float64)
     nev = X.shape[1]
     # initial Rayleigh-Ritz on the starting block

@@ -125,12 +125,74 @@ def apply_normalized_sparse(rowptr, col, w, X):
     return X - s[:, None] * (A @ (s[:, None] * X))
 
 
-def operator(rowptr, col, w, problem):
+def omp_operator(rowptr, col, w, threads=None):
+    """Z -> L_C Z as a callable over the oracle's C/OpenMP loop
+    (oracle/csrc/lap_omp.c): the same difference form as `apply`, each row's
+    entries summed in CSR order, for graphs too large for `apply`.  The CSR
+    arrays are converted once, here."""
+    import ctypes
+    from . import _native
+    lib = _native.lib()
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    cc = np.ascontiguousarray(col, dtype=np.int32)
+    ww = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    n = rp.size - 1
+    nt = _native.default_threads() if threads is None else int(threads)
+
+    def op(Z):
+        Z = np.asarray(Z, dtype=np.float64)
+        squeeze = Z.ndim == 1
+        Zc = np.ascontiguousarray(Z.reshape(n, -1))
+        Y = np.empty_like(Zc)
+        lib.oracle_lap_apply(n, rp.ctypes.data, cc.ctypes.data,
+                             None if ww is None else ww.ctypes.data,
+                             Zc.ctypes.data, Zc.shape[1], Y.ctypes.data, nt)
+        return Y[:, 0] if squeeze else Y
+    return op
+
+
+def apply_omp(rowptr, col, w, X, threads=None):
+    """Y = L_C X through `omp_operator` (one call)."""
+    return omp_operator(rowptr, col, w, threads)(X)
+
+
+def operator(rowptr, col, w, problem, fast=False):
     """The matrix of the eigenproblem as a callable: L_C for the
-    combinatorial and generalized problems, L_N for the normalized one."""
-    if problem == NORMALIZED:
-        return lambda Z: apply_normalized(rowptr, col, w, Z)
-    return lambda Z: apply(rowptr, col, w, Z)
+    combinatorial and generalized problems, L_N for the normalized one.
+    fast: use the C/OpenMP loop (`omp_operator`); L_N is then applied as
+    D^-1/2 L_C D^-1/2, the same operator as `apply_normalized`."""
+    if not fast:
+        if problem == NORMALIZED:
+            return lambda Z: apply_normalized(rowptr, col, w, Z)
+        return lambda Z: apply(rowptr, col, w, Z)
+    LC = omp_operator(rowptr, col, w)
+    if problem != NORMALIZED:
+        return LC
+    d = degrees_fast(rowptr, col, w)
+    if (d <= 0).any():
+        raise ValueError("L_N needs every degree > 0")
+    s = 1.0 / np.sqrt(d)
+
+    def op(Z):
+        Z = np.asarray(Z, dtype=np.float64)
+        if Z.ndim == 1:
+            return s * LC(s * Z)
+        return s[:, None] * LC(s[:, None] * Z)
+    return op
+
+
+def degrees_fast(rowptr, col, w=None):
+    """Weighted degrees for large graphs: each row's weights summed in FP64
+    in CSR order (`degrees` rounds the exact sum once instead and is slow on
+    large graphs; the two differ by at most a few units in the last place).
+    Unit weights: the row lengths, exactly."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    if w is None:
+        return np.diff(rowptr).astype(np.float64)
+    ww = np.asarray(w, dtype=np.float64)
+    n = rowptr.size - 1
+    r = np.repeat(np.arange(n, dtype=np.int64), np.diff(rowptr))
+    return np.bincount(r, weights=ww, minlength=n).astype(np.float64)
 
 
 def dense_normalized(rowptr, col, w, n=None):

@@ -35,13 +35,14 @@ def jacobi(R, d):
 
 
 def chebyshev(rowptr, col, w, R, degree, lo, hi, dinv=None,
-              problem=laplacian.COMBINATORIAL):
+              problem=laplacian.COMBINATORIAL, op=None):
     """h = p(L) r column-wise by `degree` Chebyshev steps (degree SpMMs).
 
     With dinv given, solves (D^-1 L) h = D^-1 r instead (generalized problem);
-    with problem NORMALIZED the matrix is L_N.
+    with problem NORMALIZED the matrix is L_N.  op: the operator Z -> L Z when
+    the caller has it already (large graphs).
     """
-    L = laplacian.operator(rowptr, col, w, problem)
+    L = laplacian.operator(rowptr, col, w, problem) if op is None else op
     R = np.asarray(R, dtype=np.float64)
     c = 0.5 * (hi + lo)
     e = 0.5 * (hi - lo)

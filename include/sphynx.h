@@ -12,7 +12,7 @@
  *     optional edge weights w[nnz] (float32 or float64; NULL = unit), optional
  *     vertex weights vwgt[n] (positive int32; NULL = unit).  The pattern and
  *     the weights must be symmetric, with no self-loops and no duplicate
- *     entries.  Column indices need not be sorted.
+ *     entries, and the column indices of each row strictly increasing.
  *   - Dense blocks of vectors are row-major (vertex-major): entry (i, c) of an
  *     n x m block lives at X[i * m + c].
  *   - "device" pointers are HIP device memory on the handle's device; "host"
@@ -194,8 +194,9 @@ void sphx_options_default(sphx_options *opt, int graph_is_regular, int precond);
  * w: device edge weights of type w_dtype (SPHX_F32/SPHX_F64) or NULL with
  * SPHX_UNIT.  vwgt: device int32[n] vertex weights (>= 1) or NULL (unit).
  * Unless flags has SPHX_SKIP_VALIDATE, the arrays are checked on the device
- * (monotone row_ptr, 0 <= col < n, no self-loops, no duplicates, symmetric
- * pattern and weights, weights finite and > 0): errors SPHX_E_BAD_GRAPH,
+ * (row_ptr monotone from 0 to nnz, 0 <= col < n, columns strictly increasing
+ * within each row -- hence no duplicates --, no self-loops, symmetric pattern
+ * and weights, weights finite and > 0): errors SPHX_E_BAD_GRAPH,
  * SPHX_E_SELF_LOOP, SPHX_E_NOT_SYMMETRIC, SPHX_E_BAD_WEIGHT.  Connectivity is
  * not checked: with c components, eigenvalue 0 has multiplicity c.
  * Requires 1 <= n < 2^31 and nnz < 2^31 (int32 row_ptr) or < 2^62. */
@@ -212,13 +213,21 @@ int sphx_graph_info(sphx_handle *h, sphx_graph *g, int *is_regular,
 
 /* --------------------------------------------------------------- workspace */
 
-/* Device bytes needed by sphx_eigensolve / sphx_partition / sphx_eig_backward
- * for this graph, nev and options (an upper bound for all of them). */
+/* Device bytes needed by sphx_eigensolve (nev), sphx_partition (any K with
+ * floor(log2 K) + 1 = nev), sphx_eig_backward (nev) and the operator calls
+ * (m <= nev) for this graph and options: an upper bound for all of them. */
 int sphx_workspace_size(sphx_handle *h, sphx_graph *g, int nev,
                         const sphx_options *opt, size_t *bytes);
-/* Hand the library a device workspace (borrowed).  Calls that need more than
- * `bytes` allocate (and cache) their own instead.  NULL detaches it. */
+/* Hand the library a device workspace (borrowed, at least 256-byte aligned).
+ * A call that needs more than `bytes` allocates (and caches in the handle)
+ * its own instead; with a workspace of sphx_workspace_size bytes the calls
+ * above allocate no device memory.  NULL detaches it. */
 int sphx_set_workspace(sphx_handle *h, void *dev_ptr, size_t bytes);
+/* Device bytes the handle currently owns as its own cached workspace (0 when
+ * every call so far fit the caller's workspace). */
+int sphx_workspace_owned(const sphx_handle *h, size_t *bytes);
+/* Free the handle's own cached workspace (synchronises the stream). */
+int sphx_workspace_release(sphx_handle *h);
 
 /* -------------------------------------------------------------- operators */
 
@@ -357,17 +366,25 @@ int sphx_poly_apply(sphx_handle *h, sphx_graph *g, int problem, int nroots,
  * Eigenvector terms inside the block use the computed pairs; the rest of the
  * spectrum enters through mu_k solving (L - lambda_k B) mu_k =
  * g_k - B V V^T g_k with V^T B mu_k = 0 (projected, Jacobi-preconditioned
- * conjugate gradients to relative residual cg_tol, at most cg_max_iter).
+ * conjugate gradients, all columns at once, at most cg_max_iter steps, until
+ * every column's residual r satisfies sqrt(r^T J r) <= cg_tol sqrt(f^T J f),
+ * f the right-hand side and J the inverted diagonal of L - lambda_k B).  The
+ * solve needs lambda_k separated from the eigenvalues outside the block.
  * For SPHX_NORMALIZED (eigvecs y = D^1/2 x of unit 2-norm) the gradient is
  * the generalized one for x with dl/dx = D^1/2 dl/dy, plus, on each edge
  * {i, j}, t_i + t_j with t_i = sum_k (dl/dy_ik) y_ik / (2 d_i) from the
  * dependence of D^1/2 on w.
  * The graph must carry F64 weights or unit weights.
- * Returns SPHX_NOT_CONVERGED if a CG solve stopped at cg_max_iter. */
+ * Returns SPHX_NOT_CONVERGED if a CG solve stopped at cg_max_iter (or lost
+ * positive curvature); grad_w then holds the gradient of the last iterate. */
 int sphx_eig_backward(sphx_handle *h, sphx_graph *g, int problem, int nev,
                       const double *eigvals, const void *eigvecs,
                       const double *g_vals, const void *g_vecs,
                       double cg_tol, int cg_max_iter, void *grad_w);
+/* CG steps of the handle's last sphx_eig_backward and the largest final
+ * relative residual over its columns (0 when no eigenvector term). */
+int sphx_backward_info(const sphx_handle *h, int *cg_iterations,
+                       double *cg_rel_residual);
 
 /* ------------------------------------------------------- kernel test hooks */
 /* The dense kernels of one LOBPCG iteration (Algorithm 1: the block Gram

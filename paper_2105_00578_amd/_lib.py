@@ -70,6 +70,9 @@ def _load():
         "sphx_workspace_size": (C.c_int, [vp, vp, C.c_int, C.POINTER(_Options),
                                           C.POINTER(C.c_size_t)]),
         "sphx_set_workspace": (C.c_int, [vp, vp, C.c_size_t]),
+        "sphx_workspace_owned": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
+        "sphx_backward_info": (C.c_int, [vp, C.POINTER(C.c_int), dp]),
+        "sphx_workspace_release": (C.c_int, [vp]),
         "sphx_laplacian_apply": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int, vp, vp]),
         "sphx_poly_roots": (C.c_int, [vp, vp, C.c_int, C.c_int, vp, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int)]),
@@ -261,6 +264,7 @@ class Graph:
             0 if validate else SKIP_VALIDATE, C.byref(self.g)))
 
     def info(self):
+        _attach_workspace(self.h, self, 1, Options())
         reg = C.c_int()
         mx = C.c_int64()
         avg = C.c_double()
@@ -299,6 +303,29 @@ def set_workspace(h: Handle, buf) -> None:
                                     0 if buf is None else buf.numel() * buf.element_size()))
 
 
+def workspace_owned(h: Handle) -> int:
+    """Device bytes the handle owns as its own cached workspace."""
+    b = C.c_size_t()
+    h._check(lib.sphx_workspace_owned(h.h, C.byref(b)))
+    return b.value
+
+
+def workspace_release(h: Handle) -> None:
+    """Free the handle's own cached workspace."""
+    h._check(lib.sphx_workspace_release(h.h))
+
+
+def _attach_workspace(h: Handle, g: Graph, nev: int, opts: Options) -> None:
+    """Size the workspace for (g, nev, opts) and give the library a PyTorch
+    byte buffer at least that large, so the call allocates no device memory
+    of its own (the buffer grows, never shrinks, and stays with the handle)."""
+    need = workspace_size(h, g, nev, opts)
+    have = 0 if h._ws is None else h._ws.numel()
+    if have < need:
+        torch = _torch()
+        set_workspace(h, torch.empty(need, dtype=torch.uint8, device=g.col.device))
+
+
 def laplacian_apply(h: Handle, g: Graph, X, out=None, problem: int = COMBINATORIAL):
     """Y = L X for an n x m block (float32 or float64): L_C, or L_N for the
     normalized problem."""
@@ -306,6 +333,7 @@ def laplacian_apply(h: Handle, g: Graph, X, out=None, problem: int = COMBINATORI
     X = X.contiguous()
     Y = torch.empty_like(X) if out is None else out
     m = 1 if X.dim() == 1 else X.shape[1]
+    _attach_workspace(h, g, m, Options(problem=problem, precision=MIXED))
     h._check(lib.sphx_laplacian_apply(h.h, g.g, problem, m, _dtype_code(X),
                                       C.c_void_p(_ptr(X)), C.c_void_p(_ptr(Y))))
     return Y
@@ -341,6 +369,7 @@ def precond_apply(h: Handle, g: Graph, opts: Options, R, out=None):
     H = torch.empty_like(R) if out is None else out
     m = 1 if R.dim() == 1 else R.shape[1]
     o = opts._c()
+    _attach_workspace(h, g, m, opts)
     h._check(lib.sphx_precond_apply(h.h, g.g, C.byref(o), m, _dtype_code(R),
                                     C.c_void_p(_ptr(R)), C.c_void_p(_ptr(H))))
     return H
@@ -362,6 +391,7 @@ def eigensolve(h: Handle, g: Graph, nev: int, opts: Options, X0=None, out=None,
     lam = (C.c_double * nev)()
     st = _Stats()
     o = opts._c()
+    _attach_workspace(h, g, nev, opts)
     code = lib.sphx_eigensolve(h.h, g.g, nev, C.byref(o), C.c_void_p(_ptr(X0)), lam,
                                C.c_void_p(_ptr(V)), C.byref(st))
     h._check(code, allow_warn=allow_not_converged)
@@ -423,6 +453,7 @@ def partition(h: Handle, g: Graph, K: int, opts: Options, X0=None,
     imb = C.c_double()
     st = _Stats()
     o = opts._c()
+    _attach_workspace(h, g, d, opts)
     code = lib.sphx_partition(h.h, g.g, K, C.byref(o), C.c_void_p(_ptr(X0)), lam,
                               C.c_void_p(_ptr(V)), C.c_void_p(_ptr(part)), C.byref(cut),
                               C.byref(imb), C.byref(st))
@@ -444,11 +475,20 @@ def eig_backward(h: Handle, g: Graph, problem: int, eigvals, V, g_vals=None, g_v
     if g_vecs is not None:
         g_vecs = g_vecs.to(V.device, torch.float64).contiguous()
     grad = torch.empty(g.nnz, dtype=torch.float64, device=g.col.device)
+    _attach_workspace(h, g, nev, Options(problem=problem))
     code = lib.sphx_eig_backward(h.h, g.g, problem, nev, lam, C.c_void_p(_ptr(V)), gl,
                                  C.c_void_p(_ptr(g_vecs)), cg_tol, cg_max_iter,
                                  C.c_void_p(_ptr(grad)))
     h._check(code, allow_warn=allow_not_converged)
     return grad
+
+
+def backward_info(h: Handle):
+    """(CG steps, largest final relative residual) of the last eig_backward."""
+    it = C.c_int()
+    rr = C.c_double()
+    h._check(lib.sphx_backward_info(h.h, C.byref(it), C.byref(rr)))
+    return it.value, rr.value
 
 
 def block_gram(h: Handle, X, LX, H=None, LH=None, P=None, LP=None, act=(), bdiag=None):

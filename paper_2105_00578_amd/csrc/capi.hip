@@ -736,7 +736,11 @@ int sphx_create(sphx_handle **out, int device, void *stream) {
   h->stream = static_cast<hipStream_t>(stream);
   if (hipSetDevice(device) != hipSuccess ||
       hipHostMalloc((void **)&h->pinned_status, sizeof(DevStatus)) != hipSuccess ||
-      hipHostMalloc(&h->pinned_small, 65536) != hipSuccess) {
+      hipHostMalloc(&h->pinned_small, kPinnedSmallBytes) != hipSuccess ||
+      hipMalloc((void **)&h->flags_dev, 256) != hipSuccess) {
+    if (h->pinned_status) (void)hipHostFree(h->pinned_status);
+    if (h->pinned_small) (void)hipHostFree(h->pinned_small);
+    if (h->flags_dev) (void)hipFree(h->flags_dev);
     delete h;
     return SPHX_E_HIP;
   }
@@ -750,6 +754,7 @@ int sphx_destroy(sphx_handle *h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
   if (h->ws_own) (void)hipFree(h->ws_own);
+  if (h->flags_dev) (void)hipFree(h->flags_dev);
   if (h->pinned_status) (void)hipHostFree(h->pinned_status);
   if (h->pinned_small) (void)hipHostFree(h->pinned_small);
   delete h;
@@ -821,14 +826,8 @@ int sphx_graph_create(sphx_handle *h, int64_t n, int64_t nnz, const void *row_pt
   g->wdt = w_dtype;
   g->vwgt = vwgt;
   if (!(flags & SPHX_SKIP_VALIDATE)) {
-    int32_t *fd = nullptr;
-    if (hipMallocAsync((void **)&fd, 256, h->stream) != hipSuccess) {
-      delete g;
-      return SPHX_E_HIP;
-    }
-    int st = validate_graph(g, h->stream, fd, static_cast<int *>(h->pinned_small));
-    (void)hipFreeAsync(fd, h->stream);
-    (void)hipStreamSynchronize(h->stream);
+    // the flags live in the handle's own 256 device bytes (no allocation)
+    int st = validate_graph(g, h->stream, h->flags_dev, static_cast<int *>(h->pinned_small));
     if (st != SPHX_OK) {
       delete g;
       return st;
@@ -902,7 +901,9 @@ static size_t solve_bytes(sphx_graph *g, int nev, int precision, int K, bool spl
 int sphx_workspace_size(sphx_handle *h, sphx_graph *g, int nev, const sphx_options *opt,
                         size_t *bytes) {
   if (!h || !g || !opt || !bytes || nev < 1 || nev > kMaxNev) return SPHX_E_INVALID_ARG;
-  int K = 1 << (nev - 1);
+  // the largest K with floor(log2 K) + 1 = nev: the split and quality scratch
+  // grow with K, so this bounds every partition into d = nev coordinates
+  int K = (1 << nev) - 1;
   size_t a = solve_bytes(g, nev, opt->precision, K, true, poly_degree_of(opt),
                          ord_bytes_of(g, opt));
   size_t b = adjoint_scratch_bytes(g->n, nev) + plan_bytes(g) + sizeof(double) * 2 * g->n +
@@ -915,6 +916,25 @@ int sphx_set_workspace(sphx_handle *h, void *ptr, size_t bytes) {
   if (!h) return SPHX_E_INVALID_ARG;
   h->ws_user = ptr;
   h->ws_user_bytes = ptr ? bytes : 0;
+  return SPHX_OK;
+}
+
+int sphx_workspace_owned(const sphx_handle *h, size_t *bytes) {
+  if (!h || !bytes) return SPHX_E_INVALID_ARG;
+  *bytes = h->ws_own_bytes;
+  return SPHX_OK;
+}
+
+int sphx_workspace_release(sphx_handle *h) {
+  if (!h) return SPHX_E_INVALID_ARG;
+  if (h->ws_own) {
+    if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+    if (h->stream) SPHX_HIP(h, hipStreamSynchronize(h->stream));
+    else SPHX_HIP(h, hipDeviceSynchronize());
+    SPHX_HIP(h, hipFree(h->ws_own));
+  }
+  h->ws_own = nullptr;
+  h->ws_own_bytes = 0;
   return SPHX_OK;
 }
 
@@ -1353,17 +1373,11 @@ int sphx_quality(sphx_handle *h, sphx_graph *g, const int32_t *part, int K, doub
                  double *cut2x, double *imbalance, int64_t *part_weights) {
   if (!h || !g || !part || K < 1) return SPHX_E_INVALID_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
-  if (g->wdt != SPHX_UNIT && !g->stats_valid) {
-    size_t need = align_up(sizeof(double) * g->n, 256) + 4 * kDegBlocksMax * sizeof(double) + 512;
-    char *ws = nullptr;
-    SPHX_TRY(get_workspace(h, need, &ws));
-    DegreeStats ds;
-    SPHX_TRY(compute_degrees(g, reinterpret_cast<double *>(ws), nullptr,
-                             ws + align_up(sizeof(double) * g->n, 256), &ds, h->pinned_small,
-                             h->stream));
-  }
   char *ws = nullptr;
   SPHX_TRY(get_workspace(h, quality_scratch_bytes(K), &ws));
+  // the exact cut's fixed-point exponent needs the weight range (the
+  // quality scratch holds the range pass's block partials)
+  SPHX_TRY(weight_range(g, ws, h->pinned_small, h->stream));
   std::string err;
   double c = 0.0;
   int r = quality(g, part, K, &c, imbalance, part_weights, ws, h->pinned_small, h->stream, &err);
@@ -1379,17 +1393,10 @@ int sphx_refine(sphx_handle *h, sphx_graph *g, int K, int32_t *part, double eps,
   if (!h || !g || !part || K < 1 || max_passes < 0 || !(eps >= 0.0) || !std::isfinite(eps))
     return SPHX_E_INVALID_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
-  if (g->wdt != SPHX_UNIT && !g->stats_valid) {
-    size_t need = align_up(sizeof(double) * g->n, 256) + 4 * kDegBlocksMax * sizeof(double) + 512;
-    char *ws = nullptr;
-    SPHX_TRY(get_workspace(h, need, &ws));
-    DegreeStats ds;
-    SPHX_TRY(compute_degrees(g, reinterpret_cast<double *>(ws), nullptr,
-                             ws + align_up(sizeof(double) * g->n, 256), &ds, h->pinned_small,
-                             h->stream));
-  }
   char *ws = nullptr;
   SPHX_TRY(get_workspace(h, refine_scratch_bytes(g->n, K), &ws));
+  // fixed-point exponent of the exact gains and cuts: the weight range
+  SPHX_TRY(weight_range(g, ws, h->pinned_small, h->stream));
   std::string err;
   int r = refine(g, part, K, eps, max_passes, cut, imbalance, passes, moves, ws,
                  h->pinned_small, h->stream, &err);
@@ -1508,11 +1515,23 @@ int sphx_eig_backward(sphx_handle *h, sphx_graph *g, int problem, int nev,
     return set_err(h, SPHX_E_INVALID_ARG, "isolated vertex");
   char *scratch = a.take<char>(adjoint_scratch_bytes(g->n, nev));
   std::string err;
+  h->last_cg_iters = 0;
+  h->last_cg_relres = 0.0;
   int r = eig_backward(g, plan, problem, nev, eigvals, (const double *)eigvecs, g_vals,
                        (const double *)g_vecs, cg_tol, cg_max_iter, d64, (double *)grad_w,
-                       scratch, h->pinned_small, h->stream, &err);
+                       scratch, h->pinned_small, h->stream, &err, &h->last_cg_iters,
+                       &h->last_cg_relres);
   if (r < 0) return set_err(h, r, err);
+  if (r == SPHX_NOT_CONVERGED)
+    return set_err(h, r, err.empty() ? "adjoint CG reached cg_max_iter" : err);
   return r;
+}
+
+int sphx_backward_info(const sphx_handle *h, int *cg_iterations, double *cg_rel_residual) {
+  if (!h) return SPHX_E_INVALID_ARG;
+  if (cg_iterations) *cg_iterations = h->last_cg_iters;
+  if (cg_rel_residual) *cg_rel_residual = h->last_cg_relres;
+  return SPHX_OK;
 }
 
 }  // extern "C"

@@ -95,6 +95,10 @@ struct PhaseLog {
 };
 }  // namespace sphx
 
+namespace sphx {
+constexpr size_t kPinnedSmallBytes = 65536;
+}  // namespace sphx
+
 struct sphx_handle {
   sphx::PhaseLog plog;
   int device = 0;
@@ -106,7 +110,11 @@ struct sphx_handle {
   size_t ws_own_bytes = 0;
   int timing = 0;
   sphx::DevStatus *pinned_status = nullptr;   // hipHostMalloc'ed
-  void *pinned_small = nullptr;               // 4 KiB scratch for small D2H reads
+  void *pinned_small = nullptr;               // kPinnedSmallBytes of pinned host
+                                              // memory for small D2H reads
+  int32_t *flags_dev = nullptr;               // 256 device bytes: validation flags
+  int last_cg_iters = 0;                      // of the last sphx_eig_backward
+  double last_cg_relres = 0.0;
 };
 
 struct sphx_graph {
@@ -124,6 +132,7 @@ struct sphx_graph {
   int64_t sum_deg = 0;
   double max_wdeg = 0.0;
   double wmin = 0.0, wmax = 0.0;   // edge weight range (weighted graphs)
+  int wrange_valid = 0;            // wmin / wmax computed
 };
 
 // ----------------------------------------------------------------- helpers

@@ -51,6 +51,12 @@ struct DegreeStats {
 int validate_graph(sphx_graph *g, hipStream_t s, int32_t *flags_dev, int *flags_host);
 // d64[i] = weighted degree; dT (float or double copy, may be null);
 // returns statistics through a device buffer then host.
+// Edge-weight range of a weighted graph (g->wmin, g->wmax; unit graphs: no
+// work), cached in the graph.  scratch: device, 2 doubles per block of at most
+// kWrangeBlocks blocks; pinned: host, as many.  Weights spanning more than
+// 2^40 give SPHX_E_BAD_WEIGHT (the exact fixed-point sums need less).
+constexpr int kWrangeBlocks = 1024;
+int weight_range(sphx_graph *g, void *scratch, void *pinned, hipStream_t s);
 int compute_degrees(sphx_graph *g, double *d64, float *d32, void *scratch,
                     DegreeStats *out, void *pinned, hipStream_t s);
 int build_plan(sphx_graph *g, Arena &ws, SpmmPlan *plan, const DegreeStats &st,
@@ -90,6 +96,16 @@ struct EpiPolyP {
   double inv_t, inv_t_next;
   const double *dinv;  // nullable: 1
   int last;
+};
+
+// Shifted product with dots: out = L p - lam_c b_i p (b = bd or 1), and
+// per-block partials of p^T out per column (the norm-partial layout).
+template <typename T>
+struct EpiShiftDotP {
+  T *OUT;
+  int ld;
+  const double *lam;   // device, per column
+  const double *bd;    // nullable: B = I
 };
 
 template <typename T>
@@ -139,6 +155,9 @@ template <typename T>
 int vspmm_residual(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
                    EpiResidualP<T> epi, double *norm_partials, int *n_norm_blocks,
                    hipStream_t s);
+template <typename T>
+int vspmm_shiftdot(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
+                   EpiShiftDotP<T> epi, double *partials, int *n_blocks, hipStream_t s);
 template <typename T>
 int vspmm_cheb(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
                EpiChebP<T> epi, hipStream_t s, const LaunchEvents *ev = nullptr);
@@ -245,6 +264,10 @@ int split_mj(sphx_graph *g, const T *coords, int ld, int ncoord, int K,
 
 // ---------------------------------------------------------------- quality
 size_t quality_scratch_bytes(int K);
+// 64-bit words of the pinned host buffer `quality` reads its results through
+// (the handle's kPinnedSmallBytes): the 2 x 1024 cut partials and a flag fit,
+// part weights come back in chunks of this many
+constexpr int kQualityPinnedWords = (int)(kPinnedSmallBytes / 8);
 // cut_fixed (optional): the exact cut as an integer multiple of 2^e0 (unit
 // weights: the number of cut edges), for exact comparisons
 int quality(sphx_graph *g, const int32_t *part, int K, double *cut,
@@ -260,10 +283,13 @@ int refine(sphx_graph *g, int32_t *part, int K, double eps, int max_passes, doub
 
 // ---------------------------------------------------------------- adjoint
 size_t adjoint_scratch_bytes(int64_t n, int nev);
+// cg_iters, cg_relres (nullable): CG steps taken and the largest final
+// relative residual (preconditioner norm) over the columns
 int eig_backward(sphx_graph *g, const SpmmPlan &plan, int problem, int nev,
                  const double *eigvals, const double *V, const double *g_vals,
                  const double *gV, double cg_tol, int cg_max_iter,
                  const double *d64, double *grad, void *scratch, void *pinned,
-                 hipStream_t s, std::string *err);
+                 hipStream_t s, std::string *err, int *cg_iters = nullptr,
+                 double *cg_relres = nullptr);
 
 }  // namespace sphx

@@ -110,6 +110,14 @@ __global__ __launch_bounds__(256) void k_part_weights(int64_t n, const int32_t *
 
 constexpr int kCutBlocks = 1024;
 
+// Clears n 64-bit words (a kernel rather than a memset node, so that the
+// clearing is an ordinary launch on the stream).
+__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
 double u128_to_double(unsigned __int128 v) {
   if (v == 0) return 0.0;
   int nb = 0;
@@ -137,18 +145,17 @@ int quality(sphx_graph *g, const int32_t *part, int K, double *cut, double *imba
   a.base = static_cast<char *>(scratch);
   unsigned long long *cp = a.take<unsigned long long>(2 * kCutBlocks);
   unsigned long long *pw = a.take<unsigned long long>(K);
-  int *bad = a.take<int>(4);
+  // the bad-part flag shares the zeroed region: one 64-bit word after pw
+  unsigned long long *bad = a.take<unsigned long long>(1);
   // the weight range (and its e0) is known from the degree pass
   int e0 = 0;
   if (g->wdt == SPHX_F32) e0 = fixed_exponent<float>(g->wmin);
   if (g->wdt == SPHX_F64) e0 = fixed_exponent<double>(g->wmin);
-  if (hipMemsetAsync(pw, 0, sizeof(unsigned long long) * K, s) != hipSuccess ||
-      hipMemsetAsync(bad, 0, sizeof(int) * 4, s) != hipSuccess) {
-    *err = "quality: memset failed";
-    return SPHX_E_HIP;
-  }
+  const int64_t nz = (int64_t)(reinterpret_cast<char *>(bad + 1) -
+                               reinterpret_cast<char *>(pw)) / 8;
+  hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(nz, 256, 1024)), dim3(256), 0, s, pw, nz);
   hipLaunchKernelGGL(k_part_weights, dim3(grid_for(g->n, 256 * 16, 1024)), dim3(256), 0, s,
-                     g->n, part, g->vwgt, K, pw, bad);
+                     g->n, part, g->vwgt, K, pw, reinterpret_cast<int *>(bad));
   const unsigned nb = grid_for(g->nnz, kCutChunk, kCutBlocks);
   auto go = [&](auto it, auto wt) {
     using IdxT = decltype(it);
@@ -169,33 +176,43 @@ int quality(sphx_graph *g, const int32_t *part, int K, double *cut, double *imba
     *err = "quality kernel launch failed";
     return SPHX_E_HIP;
   }
-  std::vector<unsigned long long> hc(2 * nb), hw(K);
-  int hbad = 0;
-  if (hipMemcpyAsync(hc.data(), cp, sizeof(unsigned long long) * 2 * nb,
-                     hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(hw.data(), pw, sizeof(unsigned long long) * K, hipMemcpyDeviceToHost,
+  // results come back through the pinned host buffer (kQualityPinnedWords
+  // 64-bit words): the cut partials and flag first, then the part weights in
+  // chunks, so no host memory is allocated here
+  unsigned long long *hb = static_cast<unsigned long long *>(pinned);
+  if (hipMemcpyAsync(hb, cp, sizeof(unsigned long long) * 2 * nb, hipMemcpyDeviceToHost,
                      s) != hipSuccess ||
-      hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(hb + 2 * kCutBlocks, bad, sizeof(unsigned long long),
+                     hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     *err = "quality: copy failed";
     return SPHX_E_HIP;
   }
-  if (hbad) {
+  if (hb[2 * kCutBlocks]) {
     *err = "part id out of range [0, K)";
     return SPHX_E_INVALID_ARG;
   }
   unsigned __int128 tot = 0;
   for (unsigned b = 0; b < nb; ++b)
-    tot += ((unsigned __int128)hc[2 * b + 1] << 64) + hc[2 * b];
+    tot += ((unsigned __int128)hb[2 * b + 1] << 64) + hb[2 * b];
   if (cut_fixed) *cut_fixed = tot;
   double c = u128_to_double(tot);
   if (g->wdt != SPHX_UNIT) c = std::ldexp(c, e0);
   if (cut) *cut = c;
   unsigned long long mx = 0, sum = 0;
-  for (int k = 0; k < K; ++k) {
-    mx = std::max(mx, hw[k]);
-    sum += hw[k];
-    if (part_weights) part_weights[k] = (int64_t)hw[k];
+  for (int k0 = 0; k0 < K; k0 += kQualityPinnedWords) {
+    const int cnt = std::min(K - k0, kQualityPinnedWords);
+    if (hipMemcpyAsync(hb, pw + k0, sizeof(unsigned long long) * cnt, hipMemcpyDeviceToHost,
+                       s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      *err = "quality: copy failed";
+      return SPHX_E_HIP;
+    }
+    for (int k = 0; k < cnt; ++k) {
+      mx = std::max(mx, hb[k]);
+      sum += hb[k];
+      if (part_weights) part_weights[k0 + k] = (int64_t)hb[k];
+    }
   }
   if (imbalance) *imbalance = sum ? (double)(mx * (unsigned long long)K) / (double)sum : 1.0;
   return SPHX_OK;

@@ -44,8 +44,11 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, int64_t nnz,
         WT wk = w[k];
         if (!(wk > WT(0)) || !(wk < WT(INFINITY))) f |= F_BAD_WEIGHT;
       }
-      // symmetric partner (i in row j), binary search
+      // symmetric partner (i in row j), binary search over row j, whose
+      // bounds are checked first (a malformed row_ptr must not send the
+      // search outside col[0..nnz))
       int64_t lo = rp[j], hi = rp[j + 1] - 1;
+      if (lo < 0 || hi + 1 < lo || hi + 1 > nnz) { f |= F_BAD_GRAPH; continue; }
       bool found = false;
       int64_t kk = -1;
       while (lo <= hi) {
@@ -314,37 +317,44 @@ int validate_graph(sphx_graph *g, hipStream_t s, int32_t *flags_dev, int *flags_
 
 constexpr int kDegBlocks = 1024;
 
+int weight_range(sphx_graph *g, void *scratch, void *pinned, hipStream_t s) {
+  if (g->wdt == SPHX_UNIT || g->wrange_valid) return SPHX_OK;
+  double *stats = static_cast<double *>(scratch);
+  double *host = static_cast<double *>(pinned);
+  const unsigned gw = grid_for(g->nnz, 256, kWrangeBlocks);
+  if (g->wdt == SPHX_F32)
+    hipLaunchKernelGGL((k_wrange<float>), dim3(gw), dim3(256), 0, s, g->nnz,
+                       (const float *)g->w, stats);
+  else
+    hipLaunchKernelGGL((k_wrange<double>), dim3(gw), dim3(256), 0, s, g->nnz,
+                       (const double *)g->w, stats);
+  SPHX_HIP(g->h, hipGetLastError());
+  SPHX_HIP(g->h, hipMemcpyAsync(host, stats, sizeof(double) * 2 * gw,
+                                hipMemcpyDeviceToHost, s));
+  SPHX_HIP(g->h, hipStreamSynchronize(s));
+  double a = 0, b = 1e300;
+  for (unsigned q = 0; q < gw; ++q) {
+    a = std::max(a, host[q * 2]);
+    b = std::min(b, host[q * 2 + 1]);
+  }
+  int ea, eb;
+  std::frexp(a, &ea);
+  std::frexp(b, &eb);
+  if (g->nnz > 0 && ea - eb > 40)
+    return set_err(g->h, SPHX_E_BAD_WEIGHT,
+                   "edge weights span more than a factor 2^40 (exact sums unsupported)");
+  g->wmax = a;
+  g->wmin = b;
+  g->wrange_valid = 1;
+  return SPHX_OK;
+}
+
 int compute_degrees(sphx_graph *g, double *d64, float *d32, void *scratch,
                     DegreeStats *out, void *pinned, hipStream_t s) {
   double *stats = static_cast<double *>(scratch);
   double *host = static_cast<double *>(pinned);
   // edge-weight range: e0 of the exact degree sums and of the exact cut
-  if (g->wdt != SPHX_UNIT && !g->stats_valid) {
-    unsigned gw = grid_for(g->nnz, 256, 1024);
-    if (g->wdt == SPHX_F32)
-      hipLaunchKernelGGL((k_wrange<float>), dim3(gw), dim3(256), 0, s, g->nnz,
-                         (const float *)g->w, stats);
-    else
-      hipLaunchKernelGGL((k_wrange<double>), dim3(gw), dim3(256), 0, s, g->nnz,
-                         (const double *)g->w, stats);
-    SPHX_HIP(g->h, hipGetLastError());
-    SPHX_HIP(g->h, hipMemcpyAsync(host, stats, sizeof(double) * 2 * gw,
-                                  hipMemcpyDeviceToHost, s));
-    SPHX_HIP(g->h, hipStreamSynchronize(s));
-    double a = 0, b = 1e300;
-    for (unsigned q = 0; q < gw; ++q) {
-      a = std::max(a, host[q * 2]);
-      b = std::min(b, host[q * 2 + 1]);
-    }
-    g->wmax = a;
-    g->wmin = b;
-    int ea, eb;
-    std::frexp(a, &ea);
-    std::frexp(b, &eb);
-    if (g->nnz > 0 && ea - eb > 40)
-      return set_err(g->h, SPHX_E_BAD_WEIGHT,
-                     "edge weights span more than a factor 2^40 (exact sums unsupported)");
-  }
+  SPHX_TRY(weight_range(g, scratch, pinned, s));
   int e0 = 0;
   if (g->wdt == SPHX_F32) e0 = fixed_exponent<float>(g->wmin);
   if (g->wdt == SPHX_F64) e0 = fixed_exponent<double>(g->wmin);

@@ -179,6 +179,34 @@ struct VResidual {
 };
 
 template <typename T, int VB, int NV>
+struct VShiftDot {
+  EpiShiftDotP<T> p;
+  int m;
+  static constexpr bool kNorms = true;
+  using V = typename Vec<T, VB>::type;
+  static constexpr int E = Vec<T, VB>::E;
+  __device__ void row(int64_t i, const V (&xi)[NV], const V (&acc)[NV], double *n1,
+                      double *) const {
+    const double b = p.bd ? p.bd[i] : 1.0;
+    V *out = reinterpret_cast<V *>(p.OUT + i * p.ld);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      V o;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int c = v * E + e;
+        const double x = double(xi[v][e]);
+        const double lc = c < m ? p.lam[c] : 0.0;
+        const double y = double(acc[v][e]) - b * lc * x;
+        o[e] = T(y);
+        if (c < m) n1[c] += x * y;
+      }
+      out[v] = o;
+    }
+  }
+};
+
+template <typename T, int VB, int NV>
 struct VCheb {
   EpiChebP<T> p;
   static constexpr bool kNorms = false;
@@ -511,7 +539,9 @@ int dispatch_types(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, cons
     else col = g->col;
     Csr<IdxT, WT> A{static_cast<const IdxT *>(g->rowptr), col, static_cast<const WT *>(g->w)};
     EpiT<T, VB, NV> epi{p};
-    if constexpr (std::is_same_v<EpiT<T, VB, NV>, VResidual<T, VB, NV>>) epi.m = m;
+    if constexpr (std::is_same_v<EpiT<T, VB, NV>, VResidual<T, VB, NV>> ||
+                  std::is_same_v<EpiT<T, VB, NV>, VShiftDot<T, VB, NV>>)
+      epi.m = m;
     run_vec<T, VB, NV>(A, g->n, plan, X, ld, epi, partials, nparts, m, s, ev);
   };
   if (g->rp64) {
@@ -579,6 +609,11 @@ int vspmm_residual(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int 
   return dispatch_nv<T, VResidual>(g, plan, X, ld, epi, m, norm_partials, n_norm_blocks, s);
 }
 template <typename T>
+int vspmm_shiftdot(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
+                   EpiShiftDotP<T> epi, double *partials, int *n_blocks, hipStream_t s) {
+  return dispatch_nv<T, VShiftDot>(g, plan, X, ld, epi, m, partials, n_blocks, s);
+}
+template <typename T>
 int vspmm_cheb(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
                EpiChebP<T> epi, hipStream_t s, const LaunchEvents *ev) {
   return dispatch_nv<T, VCheb>(g, plan, X, ld, epi, m, nullptr, nullptr, s, ev);
@@ -595,6 +630,8 @@ int vspmm_poly(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
                               EpiStoreP<T>, hipStream_t);                                  \
   template int vspmm_residual<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,      \
                                  EpiResidualP<T>, double *, int *, hipStream_t);           \
+  template int vspmm_shiftdot<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,      \
+                                 EpiShiftDotP<T>, double *, int *, hipStream_t);           \
   template int vspmm_cheb<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,          \
                              EpiChebP<T>, hipStream_t, const LaunchEvents *);              \
   template int vspmm_poly<T>(sphx_graph *, const SpmmPlan &, const T *, int, int,          \

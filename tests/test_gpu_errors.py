@@ -63,3 +63,15 @@ def test_argument_codes(handle):
     rp2, col2, _ = upload(g2)
     G2 = sx.Graph(handle, rp2, col2)
     assert _code(lambda: sx.eigensolve(handle, G2, 2, sx.Options(problem=sx.GENERALIZED))) == -1
+
+
+def test_malformed_row_ptr_of_a_neighbour_row(handle):
+    """A neighbour row whose bounds leave [0, nnz] is rejected (code -2)
+    before the symmetry search would read col[] outside the array."""
+    col = _t([1, 0, 2, 1], np.int32)
+    # row 2 claims entries up to 1000 although nnz = 4 (row 1 searches row 2)
+    assert _code(lambda: sx.Graph(handle, _t([0, 1, 3, 1000], np.int32), col)) == -2
+    # row_ptr[n] > nnz by one
+    assert _code(lambda: sx.Graph(handle, _t([0, 1, 3, 5], np.int32), col)) == -2
+    # a negative row bound in the middle
+    assert _code(lambda: sx.Graph(handle, _t([0, 1, -5, 4], np.int32), col)) == -2

@@ -292,6 +292,21 @@ int sphx_quality(sphx_handle *h, sphx_graph *g, const int32_t *part, int K,
                  double *cut, double *cut2x, double *imbalance,
                  int64_t *part_weights);
 
+/* sphx_quality with no allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as sphx_quality.
+ * Its scratch (cut partials, part-weight counters, flag) is a fixed 1 MiB
+ * array in the library's code object, one copy per GPU, resolved when the
+ * first handle on that GPU is created; results come back through the
+ * handle's pinned host buffer.  No device or host memory is allocated.
+ * K above 65536 gives SPHX_E_WORKSPACE.  Every call on one GPU shares that
+ * GPU's array and leaves its contents behind (each call clears what it
+ * needs): calls that overlap on one GPU (other threads, other streams)
+ * race and must not be issued. */
+int sphx_quality_noalloc(sphx_handle *h, sphx_graph *g, const int32_t *part, int K,
+                         double *cut, double *cut2x, double *imbalance,
+                         int64_t *part_weights);
+
 /* Greedy refinement of a K-way partition (Sec. 7 proposes a greedy
  * improvement step for the cut of the spectral partition; balance as in
  * Sec. 3.1: every part weight W_k below W_avg (1 + eps), eps = 0.01 in the

@@ -14,7 +14,7 @@ from ._lib import (  # noqa: F401
     status_string, num_eigenvectors, options_default,
     laplacian_apply, precond_apply, poly_roots, poly_apply, eigensolve, split, quality, refine, partition,
     eig_backward, workspace_size, set_workspace, workspace_owned, workspace_release,
-    backward_info,
+    quality_noalloc, backward_info,
     COMBINATORIAL, GENERALIZED, NORMALIZED, PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHEBYSHEV, PRECOND_GMRES,
     FP64, MIXED, INIT_RANDOM, INIT_PIECEWISE, INIT_USER,
 )

@@ -73,6 +73,8 @@ def _load():
         "sphx_workspace_owned": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
         "sphx_backward_info": (C.c_int, [vp, C.POINTER(C.c_int), dp]),
         "sphx_workspace_release": (C.c_int, [vp]),
+        "sphx_quality_noalloc": (C.c_int, [vp, vp, vp, C.c_int, dp, dp, dp,
+                                           C.POINTER(C.c_int64)]),
         "sphx_laplacian_apply": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int, vp, vp]),
         "sphx_poly_roots": (C.c_int, [vp, vp, C.c_int, C.c_int, vp, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int)]),
@@ -420,6 +422,19 @@ def quality(h: Handle, g: Graph, part, K: int):
     part = part.contiguous()
     h._check(lib.sphx_quality(h.h, g.g, C.c_void_p(_ptr(part)), K, C.byref(cut),
                               C.byref(cut2), C.byref(imb), pw))
+    return cut.value, cut2.value, imb.value, list(pw)
+
+
+def quality_noalloc(h: Handle, g: Graph, part, K: int):
+    """As `quality`, through the entry point that allocates nothing (fixed
+    device scratch, K <= 65536)."""
+    cut = C.c_double()
+    cut2 = C.c_double()
+    imb = C.c_double()
+    pw = (C.c_int64 * K)()
+    part = part.contiguous()
+    h._check(lib.sphx_quality_noalloc(h.h, g.g, C.c_void_p(_ptr(part)), K, C.byref(cut),
+                                      C.byref(cut2), C.byref(imb), pw))
     return cut.value, cut2.value, imb.value, list(pw)
 
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "kernels.h"
@@ -35,6 +36,37 @@ int get_workspace(sphx_handle *h, size_t need, char **out) {
   }
   *out = static_cast<char *>(h->ws_own);
   return SPHX_OK;
+}
+
+// Device scratch of sphx_quality_noalloc: a fixed array in the library's
+// code object, so that entry point never allocates.  Each GPU holds its own
+// copy; its address on a device is resolved once (hipGetSymbolAddress, with
+// that device current) when the first handle on that device is created, and
+// only that address is passed to kernels or copies.
+constexpr size_t kNoAllocScratchBytes = size_t(1) << 20;
+constexpr int kNoAllocMaxK = 65536;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocScratchBytes];
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// With `device` current: resolve this device's copy of noalloc_scratch.
+int resolve_noalloc_scratch(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return SPHX_OK;   // entry point refuses
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return SPHX_OK;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !p)
+    return SPHX_E_HIP;
+  g_noalloc_ptr[device] = p;
+  return SPHX_OK;
+}
+
+void *noalloc_scratch_ptr(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  return g_noalloc_ptr[device];
 }
 
 constexpr int kDegBlocksMax = 1024;
@@ -737,7 +769,8 @@ int sphx_create(sphx_handle **out, int device, void *stream) {
   if (hipSetDevice(device) != hipSuccess ||
       hipHostMalloc((void **)&h->pinned_status, sizeof(DevStatus)) != hipSuccess ||
       hipHostMalloc(&h->pinned_small, kPinnedSmallBytes) != hipSuccess ||
-      hipMalloc((void **)&h->flags_dev, 256) != hipSuccess) {
+      hipMalloc((void **)&h->flags_dev, 256) != hipSuccess ||
+      resolve_noalloc_scratch(device) != SPHX_OK) {
     if (h->pinned_status) (void)hipHostFree(h->pinned_status);
     if (h->pinned_small) (void)hipHostFree(h->pinned_small);
     if (h->flags_dev) (void)hipFree(h->flags_dev);
@@ -1377,6 +1410,26 @@ int sphx_quality(sphx_handle *h, sphx_graph *g, const int32_t *part, int K, doub
   SPHX_TRY(get_workspace(h, quality_scratch_bytes(K), &ws));
   // the exact cut's fixed-point exponent needs the weight range (the
   // quality scratch holds the range pass's block partials)
+  SPHX_TRY(weight_range(g, ws, h->pinned_small, h->stream));
+  std::string err;
+  double c = 0.0;
+  int r = quality(g, part, K, &c, imbalance, part_weights, ws, h->pinned_small, h->stream, &err);
+  if (r != SPHX_OK) return set_err(h, r, err);
+  if (cut) *cut = c;
+  if (cut2x) *cut2x = 2.0 * c;
+  return SPHX_OK;
+}
+
+int sphx_quality_noalloc(sphx_handle *h, sphx_graph *g, const int32_t *part, int K,
+                         double *cut, double *cut2x, double *imbalance,
+                         int64_t *part_weights) {
+  if (!h || !g || !part || K < 1) return SPHX_E_INVALID_ARG;
+  if (K > kNoAllocMaxK || quality_scratch_bytes(K) > kNoAllocScratchBytes)
+    return set_err(h, SPHX_E_WORKSPACE,
+                   "sphx_quality_noalloc: K above its fixed scratch limit of 65536 parts");
+  if (hipSetDevice(h->device) != hipSuccess) return SPHX_E_HIP;
+  char *ws = static_cast<char *>(noalloc_scratch_ptr(h->device));
+  if (!ws) return set_err(h, SPHX_E_HIP, "sphx_quality_noalloc: device scratch not resolved");
   SPHX_TRY(weight_range(g, ws, h->pinned_small, h->stream));
   std::string err;
   double c = 0.0;

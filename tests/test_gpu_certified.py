@@ -35,7 +35,7 @@ CASES = [
     ("rmat22", sx.FP64, 16, 5, sx.PRECOND_JACOBI, 1e-7, 1e-6, 1e-3),
     ("rmat22", sx.MIXED, 16, 5, sx.PRECOND_JACOBI, 1e-4, 1e-4, 2e-2),
     ("brick96lr", sx.FP64, 256, 9, sx.PRECOND_JACOBI, 1e-7, 1e-6, 5e-4),
-    ("brick96lr", sx.MIXED, 256, 9, sx.PRECOND_JACOBI, 1e-4, 1e-4, 2e-2),
+    ("brick96lr", sx.MIXED, 256, 9, sx.PRECOND_JACOBI, 1e-5, 1e-4, 3e-2),
     ("king512", sx.FP64, None, 7, sx.PRECOND_CHEBYSHEV, 1e-8, 1e-6, 2e-3),
     ("rmat18", sx.FP64, None, 7, sx.PRECOND_JACOBI, 1e-8, 1e-6, 1e-3),
 ]

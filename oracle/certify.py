@@ -121,7 +121,7 @@ def certified_eigenpairs(rowptr, col, w, problem, d, guards=4, tol=1e-10,
     tolv = np.array([tol] * d + [guard_tol] * guards)
     t0 = time.time()
     theta, X, its, rho = eigen.lobpcg(rowptr, col, w, problem, X0, pre, tolv,
-                                      maxiter=maxiter, op=op, bd=bd)
+                                      maxiter=maxiter, op=op, bd=bd, log=log)
     secs = time.time() - t0
     # fresh residuals of the whole block, then the bounds of the wanted part
     th_all, V_all, eps_all = residual_block(op, bd, X)

@@ -78,8 +78,16 @@ def rayleigh_ritz(S, LS, bd, nev, drop=1e-12):
     return theta[:nev], Y
 
 
+def _bnormalize(Z, LZ, bd):
+    """Scale the columns of Z (and of LZ = L Z alike) to unit B-norm (zero
+    columns stay zero)."""
+    nrm = np.sqrt(np.sum(bd[:, None] * Z * Z, axis=0))
+    nrm = np.where(nrm > 0, nrm, 1.0)
+    return Z / nrm[None, :], (None if LZ is None else LZ / nrm[None, :])
+
+
 def lobpcg(rowptr, col, w, problem, X0, precond, tol, maxiter=10000,
-           locking=True, op=None, bd=None):
+           locking=True, op=None, bd=None, log=None, log_every=50):
     """Algorithm 1 (LOBPCG, Hetmaniuk-Lehoucq form) for L x = lambda B x
     (L = L_N and B = I for the normalized problem).
 
@@ -90,7 +98,15 @@ def lobpcg(rowptr, col, w, problem, X0, precond, tol, maxiter=10000,
     directions and conjugate directions (the "I" subsets of Algorithm 1).
     op, bd: the operator Z -> L Z and the diagonal of B, when the caller has
     them already (large graphs: `laplacian.operator(..., fast=True)`).
+    log: callable(str) for a progress line every log_every iterations.
     Returns (theta, X, iterations, rho).
+
+    Numerical safeguards that leave the iteration's subspaces unchanged (RR
+    depends on span(S) only): the H and P columns are scaled to unit B-norm
+    before each Rayleigh-Ritz step, and L X is recomputed with one product per
+    iteration instead of being carried by recurrence (over thousands of
+    iterations to tolerances near 1e-10 the recurrence drifts and the
+    unscaled blocks can over- or underflow).
     """
     if bd is None:
         bd = laplacian.bdiag(rowptr, col, w, problem)
@@ -111,21 +127,24 @@ def lobpcg(rowptr, col, w, problem, X0, precond, tol, maxiter=10000,
         act = np.flatnonzero(active) if locking else np.arange(nev)
         R = LX[:, act] - (bd[:, None] * X[:, act]) * theta[act][None, :]
         H = R if precond is None else precond(R)
+        H, _ = _bnormalize(H, None, bd)
         LH = L(H)
         S = np.hstack([X, H, P])
         LS = np.hstack([LX, LH, LP])
         theta, Y = rayleigh_ritz(S, LS, bd, nev)
         X = S @ Y
-        LX = LS @ Y
+        LX = L(X)
         rho = laplacian.residual_norms(LX, X, theta, bd)
         it += 1
+        if log and it % log_every == 0:
+            log(f"lobpcg it {it}: max rho {rho.max():.3e}, "
+                f"unconverged {int((rho > tol).sum())}")
         active = rho > tol if locking else np.ones(nev, dtype=bool)
         # P_I <- [0, H_I, P_I] Y_I : the X rows of Y are dropped
         YI = Y[:, active] if locking else Y
         YI = YI.copy()
         YI[:nev, :] = 0.0
-        P = S @ YI
-        LP = LS @ YI
+        P, LP = _bnormalize(S @ YI, LS @ YI, bd)
     # final residual from an explicit product (no recurrence drift)
     LX = L(X)
     rho = laplacian.residual_norms(LX, X, theta, bd)

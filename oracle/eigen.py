@@ -71,6 +71,11 @@ def rayleigh_ritz(S, LS, bd, nev, drop=1e-12):
     sig, U = np.linalg.eigh(Gs)
     keep = sig > drop * sig.max()
     C = U[:, keep] / np.sqrt(sig[keep])[None, :]
+    # second pass: C^T Gs C is the identity up to rounding amplified by the
+    # small kept Gram eigenvalues; orthonormalise once more against it
+    G2 = C.T @ Gs @ C
+    sig2, U2 = np.linalg.eigh(0.5 * (G2 + G2.T))
+    C = C @ (U2 / np.sqrt(sig2)[None, :])
     Ap = C.T @ As @ C
     Ap = 0.5 * (Ap + Ap.T)
     theta, Z = np.linalg.eigh(Ap)
@@ -104,9 +109,9 @@ def lobpcg(rowptr, col, w, problem, X0, precond, tol, maxiter=10000,
     Numerical safeguards that leave the iteration's subspaces unchanged (RR
     depends on span(S) only): the H and P columns are scaled to unit B-norm
     before each Rayleigh-Ritz step, and L X is recomputed with one product per
-    iteration instead of being carried by recurrence (over thousands of
-    iterations to tolerances near 1e-10 the recurrence drifts and the
-    unscaled blocks can over- or underflow).
+    iteration instead of being carried by recurrence, and so is L P (over
+    hundreds of iterations to tolerances near 1e-10 the recurrences drift and
+    the unscaled blocks can over- or underflow).
     """
     if bd is None:
         bd = laplacian.bdiag(rowptr, col, w, problem)
@@ -144,7 +149,8 @@ def lobpcg(rowptr, col, w, problem, X0, precond, tol, maxiter=10000,
         YI = Y[:, active] if locking else Y
         YI = YI.copy()
         YI[:nev, :] = 0.0
-        P, LP = _bnormalize(S @ YI, LS @ YI, bd)
+        P, _ = _bnormalize(S @ YI, None, bd)
+        LP = L(P)
     # final residual from an explicit product (no recurrence drift)
     LX = L(X)
     rho = laplacian.residual_norms(LX, X, theta, bd)

@@ -23,7 +23,9 @@ grid the kernels read the column indices as int16 offsets from the row
 algorithmic count; `roofline.traffic` gives the measured bytes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-       python bench.py --workload NAME      (another configuration)
+       python bench.py --workload NAME      (another configuration; adjoint-rmat18
+                                      and adjoint-king512 time EigFn forward and
+                                      backward on the differentiation workloads)
        python bench.py --repartition        (also: greedy refinement and a
                                       warm-started repartition)
        python bench.py --only-mixed --steps 1 --warmup 0 --no-cpu-baseline
@@ -78,27 +80,91 @@ def closed_form_check(lam, V, side):
     return max(rel), trivial, sin, float(exact[m] - exact[m - 1])
 
 
-def cpu_baseline(g, m, budget_s=20.0, max_reps=10):
-    """The oracle's FP64 Laplacian product timed on the host (numpy, one
-    thread), reported in the same unit (algorithmic GB/s)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_triad_gbs(threads, n=1 << 26, reps=5):
+    """STREAM-style triad a = b + s c on the host cores (the oracle's C
+    loop), best of reps: 24 bytes per element."""
+    import numpy as np
+    from oracle import _native
+    lib = _native.lib()
+    a = np.empty(n)
+    b = np.ones(n)
+    c = np.ones(n)
+    best = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        lib.oracle_triad(n, a.ctypes.data, b.ctypes.data, c.ctypes.data, 0.5, threads)
+        dt = time.perf_counter() - t0
+        best = max(best, 24.0 * n / dt / 1e9)
+    return best
+
+
+def cpu_baseline(g, m, gpu_fp64_iterations, opts, budget_s=20.0):
+    """The oracle's LOBPCG (Algorithm 1 in FP64 with its C/OpenMP Laplacian
+    product and the same Chebyshev preconditioner: degree 25, ratio, tol) on
+    all host cores, from an N(0,1) start block, for a bounded number of
+    iterations (about budget_s); reported as the oracle's product rate in the
+    metric's unit, with the time per iteration and the time to eigenvectors
+    it implies at the GPU's FP64 iteration count."""
     import numpy as np
     import graphgen
-    from oracle import laplacian as lap
-    X = graphgen.normal_block(g.n, m, 2)
-    bytes_per = 4.0 * (g.n + 1) + 4.0 * g.nnz + 2.0 * g.n * m * 8
-    reps = 0
+    from oracle import _native, eigen, laplacian as lap, precond
+    threads = _native.default_threads()
+    op0 = lap.operator(g.rowptr, g.col, g.w, lap.COMBINATORIAL, fast=True)
+    stat = {"bytes": 0.0, "secs": 0.0, "calls": 0}
+    nnz = float(g.nnz)
+
+    def op(Z):
+        t0 = time.perf_counter()
+        Y = op0(Z)
+        stat["secs"] += time.perf_counter() - t0
+        k = 1 if Z.ndim == 1 else Z.shape[1]
+        stat["bytes"] += 4.0 * (g.n + 1) + 4.0 * nnz + 2.0 * g.n * k * 8
+        stat["calls"] += 1
+        return Y
+
+    deg = lap.degrees_fast(g.rowptr, g.col, g.w)
+    hi = precond.gershgorin_bound(deg, lap.COMBINATORIAL)
+    pre = lambda R: precond.chebyshev(g.rowptr, g.col, g.w, R, opts.cheb_degree,  # noqa: E731
+                                      hi / opts.cheb_ratio, hi, op=op)
+    X0 = graphgen.normal_block(g.n, m, 2)
+    # iterations that fit the budget: one untimed probe iteration sizes it
     t0 = time.perf_counter()
-    while reps < max_reps:
-        lap.apply(g.rowptr, g.col, None, X)
-        reps += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
+    eigen.lobpcg(g.rowptr, g.col, g.w, lap.COMBINATORIAL, X0, pre, opts.tol, maxiter=1,
+                 op=op, bd=np.ones(g.n))
+    per_it = time.perf_counter() - t0
+    its = max(2, min(gpu_fp64_iterations, int(budget_s / max(per_it, 1e-3))))
+    stat.update(bytes=0.0, secs=0.0, calls=0)
+    t0 = time.perf_counter()
+    _, _, done, rho = eigen.lobpcg(g.rowptr, g.col, g.w, lap.COMBINATORIAL, X0, pre, opts.tol,
+                                   maxiter=its, op=op, bd=np.ones(g.n))
     dt = time.perf_counter() - t0
-    return {"value": round(bytes_per * reps / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{reps} applications of the oracle's FP64 Laplacian product (numpy, "
-                      f"one thread) to the 128^3 7-point grid with an n x {m} block, "
-                      f"{dt:.1f} s"}
+    # the final explicit residual product inside lobpcg is one more call
+    per_iter = dt / max(done, 1)
+    return {
+        "value": round(stat["bytes"] / stat["secs"] / 1e9, 3), "unit": "GB/s",
+        "cores": threads, "kind": "oracle",
+        "sample": (f"{done} LOBPCG iterations of the oracle (FP64, C/OpenMP Laplacian product, "
+                   f"Chebyshev degree {opts.cheb_degree}, ratio {opts.cheb_ratio:g}) on the "
+                   f"128^3 7-point grid with d = {m}, {threads} threads, {dt:.1f} s; value = "
+                   f"its Laplacian-product rate over {stat['calls']} products"),
+        "seconds_per_iteration": round(per_iter, 3),
+        "est_time_to_eigvecs_s": round(per_iter * gpu_fp64_iterations, 1),
+        "est_basis": f"{gpu_fp64_iterations} iterations (the GPU FP64 solve's count)",
+        "converged_in_sample": bool(np.all(rho <= opts.tol)),
+        "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+        "host_triad_gbs": round(host_triad_gbs(threads), 1),
+    }
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cheb_step_grid7_128_traffic.md")
@@ -163,6 +229,12 @@ WORKLOADS = {
     "brick200": dict(graph="brick200", K=24, precond="jacobi",
                      desc="Galeri Brick3D 27-point 200^3, combinatorial, K=24 (d=5), "
                           "LOBPCG + Jacobi, tol 1e-3"),
+    "brick400": dict(graph="brick400", K=24, precond="jacobi",
+                     desc="Galeri Brick3D 27-point 400^3, combinatorial, K=24 (d=5), "
+                          "LOBPCG + Jacobi, tol 1e-3 (the paper's preconditioner table)"),
+    "brick400-cheb": dict(graph="brick400", K=24, precond="cheb",
+                          desc="Galeri Brick3D 27-point 400^3, combinatorial, K=24 (d=5), "
+                               "LOBPCG + Chebyshev degree 25, tol 1e-3"),
     "brick100-cheb": dict(graph="brick100", K=24, precond="cheb",
                           desc="Galeri Brick3D 27-point 100^3, combinatorial, K=24 (d=5), "
                                "LOBPCG + Chebyshev degree 25, tol 1e-3"),
@@ -222,10 +294,17 @@ def run(args):
         dt = (time.perf_counter() - t0) / args.steps * 1e3
         lam, V, part, cut, imb, st = outs[-1]
         last[name] = outs[-1]
-        eig_ms = [sx.eigensolve(h, G, d, o)[2].ms_total for _ in range(args.steps)]
-        h.set_timing(True)
-        sts = [sx.partition(h, G, K, o)[5] for _ in range(args.steps)]
-        h.set_timing(False)
+        if args.no_instrumented:
+            # one pass only (very large meshes): the partition's own device
+            # time stands for the time to eigenvectors (it also holds the
+            # split and cut, about 1 % of it) and phase times are not taken
+            eig_ms = [s[5].ms_total for s in outs]
+            sts = [s[5] for s in outs]
+        else:
+            eig_ms = [sx.eigensolve(h, G, d, o)[2].ms_total for _ in range(args.steps)]
+            h.set_timing(True)
+            sts = [sx.partition(h, G, K, o)[5] for _ in range(args.steps)]
+            h.set_timing(False)
         gbp = sum(s.gb_precond for s in sts)
         msp = sum(s.phases_ms["precond"] for s in sts)
         gbs = sum(s.gb_spmm for s in sts)
@@ -307,8 +386,72 @@ def run(args):
     if args.repartition:
         line["repartition"] = repartition(h, G, g, K, opts["mixed"], last["mixed"], dev)
     if headline and not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(g, d)
+        line["cpu_baseline"] = cpu_baseline(g, d, f64["iterations"], opts["fp64"])
     return line
+
+
+ADJOINT_WORKLOADS = {
+    "adjoint-rmat18": dict(graph="rmat18", precond="jacobi",
+                           desc="R-MAT scale 18 (LCC), weights U[0.5,1.5) FP64, generalized, "
+                                "7 eigenpairs (tol 1e-10), loss = sum lambda_1..4 + "
+                                "||V_1..4 - V_target||^2"),
+    "adjoint-king512": dict(graph="king512", precond="cheb",
+                            desc="9-point grid 512^2, weights U[0.5,1.5) FP64, generalized, "
+                                 "7 eigenpairs (tol 5e-10), loss = sum lambda_1..4 + "
+                                 "||V_1..4 - V_target||^2"),
+}
+
+
+def run_adjoint(args):
+    """The differentiation workloads: EigFn forward (FP64 eigensolve) and the
+    hand-written backward (adjoint kernels + projected CG), timed per step."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2105_00578_amd as sx
+
+    wl = ADJOINT_WORKLOADS[args.workload]
+    g = graphgen.config_graph(wl["graph"])
+    dev = torch.device("cuda", 0)
+    h = sx.Handle(0)
+    rp = torch.from_numpy(g.rowptr.astype(np.int32)).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    w0 = torch.from_numpy(g.w).to(dev)
+    target = torch.from_numpy(graphgen.normal_block(g.n, 4, 3) / np.sqrt(g.n)).to(dev)
+    pre = sx.PRECOND_CHEBYSHEV if wl["precond"] == "cheb" else sx.PRECOND_JACOBI
+    opts = sx.Options(problem=sx.GENERALIZED, precond=pre, precision=sx.FP64,
+                      tol=5e-10 if wl["graph"] == "king512" else 1e-10, max_iter=20000)
+    r = torch.from_numpy(np.repeat(np.arange(g.n), np.diff(g.rowptr))).to(dev)
+    bd = torch.zeros(g.n, dtype=torch.float64, device=dev).index_add_(0, r, w0)
+    fwd, bwd, cg = [], [], []
+    for step in range(args.warmup + args.steps):
+        wt = w0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, V = sx.EigFn.apply(wt, h, rp, col, 7, opts, None)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Vs = V[:, 1:5]
+        sign = torch.sign(((Vs * bd[:, None]) * target).sum(0)).detach()
+        loss = lam[1:5].sum() + ((Vs * sign - target) ** 2).sum()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if step >= args.warmup:
+            fwd.append((t1 - t0) * 1e3)
+            bwd.append((t3 - t2) * 1e3)
+            cg.append(sx.backward_info(h))
+    return {
+        "workload": args.workload, "config": f"{wl['desc']} (n={g.n}, nnz={g.nnz})",
+        "steps": args.steps, "warmup": args.warmup,
+        "forward_ms": round(float(np.median(fwd)), 3),
+        "backward_ms": round(float(np.median(bwd)), 3),
+        "cg_steps": cg[-1][0], "cg_rel_residual": cg[-1][1],
+        "data": "synthetic", "dtype": "f64",
+    }
 
 
 def repartition(h, G, g, K, o, out, dev):
@@ -364,11 +507,15 @@ def main():
     ap.add_argument("--scale-down", type=int, default=1, help="shrink the grid (tests only)")
     ap.add_argument("--only-mixed", action="store_true",
                     help="time only the mixed-precision partition (counter runs)")
-    ap.add_argument("--workload", default="grid7_128", choices=sorted(WORKLOADS),
+    ap.add_argument("--workload", default="grid7_128",
+                    choices=sorted(WORKLOADS) + sorted(ADJOINT_WORKLOADS),
                     help="configuration to time (default: the headline 128^3 grid)")
     ap.add_argument("--repartition", action="store_true",
                     help="also time the greedy refinement of the partition and a "
                          "warm-started repartition after a 1 %% weight drift")
+    ap.add_argument("--no-instrumented", action="store_true",
+                    help="skip the separate eigensolve and per-launch-event passes "
+                         "(for the largest meshes); GB/s fields are then 0")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run one plain device copy of this many bytes and exit")
     args = ap.parse_args()
@@ -379,7 +526,7 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no "
               "multi-GPU path; the whole graph is the one-GPU share.", file=sys.stderr)
         sys.exit(2)
-    line = run(args)
+    line = run_adjoint(args) if args.workload in ADJOINT_WORKLOADS else run(args)
     print(json.dumps(line), flush=True)
 
 

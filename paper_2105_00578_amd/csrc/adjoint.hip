@@ -48,30 +48,67 @@ struct AdjParams {
   double lam[kMaxNev];
 };
 
-// Gram partials: out[block][j * nev + k] = sum_i A[i,j] * wgt_i * B[i,k]
-// (A, B row-major with row strides lda, ldb)
+// Gram partials: out[block][j * nev + k] = sum_i A[i,j] * wgt_i * B[i,k] over
+// the block's rows (A, B row-major with row strides lda, ldb).  The 256
+// threads form 256 / nev^2 groups, each covering every group-th row of the
+// block for all nev^2 pairs (four independent sums per thread keep loads in
+// flight); the groups are added in LDS in group order.
 __global__ __launch_bounds__(256) void k_small_gram(const double *A, int lda, const double *Bm,
                                                     int ldb, const double *wgt, int64_t n,
                                                     int nev, double *partials,
                                                     int64_t rows_per_block) {
-  int t = threadIdx.x;
-  int j = t / nev, k = t % nev;
-  bool live = t < nev * nev;
-  int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-  int64_t r1 = min(n, r0 + rows_per_block);
-  double s = 0.0;
-  if (live)
-    for (int64_t i = r0; i < r1; ++i)
-      s += A[i * lda + j] * (wgt ? wgt[i] : 1.0) * Bm[i * ldb + k];
-  if (live) partials[(int64_t)blockIdx.x * kMaxNev * kMaxNev + t] = s;
+  __shared__ double sh[256];
+  const int np = nev * nev;
+  const int ng = 256 / np;
+  const int t = threadIdx.x;
+  const int grp = t / np, pr = t - grp * np;
+  const int j = pr / nev, k = pr - j * nev;
+  const bool live = grp < ng;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(n, r0 + rows_per_block);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (live) {
+    int64_t i = r0 + grp;
+    const int64_t st = ng;
+    for (; i + 3 * st < r1; i += 4 * st) {
+      const double a0 = A[i * lda + j], b0 = Bm[i * ldb + k];
+      const double a1 = A[(i + st) * lda + j], b1 = Bm[(i + st) * ldb + k];
+      const double a2 = A[(i + 2 * st) * lda + j], b2 = Bm[(i + 2 * st) * ldb + k];
+      const double a3 = A[(i + 3 * st) * lda + j], b3 = Bm[(i + 3 * st) * ldb + k];
+      if (wgt) {
+        s0 += a0 * wgt[i] * b0;
+        s1 += a1 * wgt[i + st] * b1;
+        s2 += a2 * wgt[i + 2 * st] * b2;
+        s3 += a3 * wgt[i + 3 * st] * b3;
+      } else {
+        s0 += a0 * b0;
+        s1 += a1 * b1;
+        s2 += a2 * b2;
+        s3 += a3 * b3;
+      }
+    }
+    for (; i < r1; i += st) s0 += A[i * lda + j] * (wgt ? wgt[i] : 1.0) * Bm[i * ldb + k];
+  }
+  sh[t] = live ? (s0 + s1) + (s2 + s3) : 0.0;
+  __syncthreads();
+  if (t < np) {
+    double a = 0.0;
+    for (int g = 0; g < ng; ++g) a += sh[g * np + t];
+    partials[(int64_t)blockIdx.x * kMaxNev * kMaxNev + t] = a;
+  }
 }
 
-__global__ void k_small_sum(const double *partials, int nblocks, int cnt, double *out) {
-  int t = threadIdx.x;
-  if (t >= cnt) return;
-  double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * kMaxNev * kMaxNev + t];
-  out[t] = s;
+// out[p] = sum over blocks of partials[block][p], p < cnt: one wavefront per
+// output, lanes strided over the blocks, then a butterfly (fixed order).
+__global__ __launch_bounds__(1024) void k_small_sum(const double *partials, int nblocks,
+                                                    int cnt, double *out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int p = wave; p < cnt; p += 16) {
+    double a = 0.0;
+    for (int b = lane; b < nblocks; b += 64) a += partials[(int64_t)b * kMaxNev * kMaxNev + p];
+    for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off);
+    if (lane == 0) out[p] = a;
+  }
 }
 
 // Vp (n x ld) = V (n x nev) with zero padding columns
@@ -327,8 +364,8 @@ __global__ __launch_bounds__(256) void k_add_vertex_terms(int64_t n, const IdxT 
   }
 }
 
-constexpr int kSmallBlocks = 256;
-constexpr int kDotBlocks = 256;
+constexpr int kSmallBlocks = 1024;
+constexpr int kDotBlocks = 1024;
 constexpr int kCgCheck = 8;   // CG steps between host reads of the flags
 
 }  // namespace
@@ -406,7 +443,7 @@ int eig_backward(sphx_graph *g, const SpmmPlan &plan, int problem, int nev,
                         double *out) {
     hipLaunchKernelGGL(k_small_gram, dim3(nsb), dim3(256), 0, s, A, lda, B, ldb, w, n, nev,
                        parts, rpb);
-    hipLaunchKernelGGL(k_small_sum, dim3(1), dim3(256), 0, s, (const double *)parts, nsb,
+    hipLaunchKernelGGL(k_small_sum, dim3(1), dim3(1024), 0, s, (const double *)parts, nsb,
                        nev * nev, out);
   };
   AdjParams prm;

@@ -50,14 +50,6 @@ __device__ __forceinline__ bool better(S c, int p, S best, int t) {
   return p >= 0 && (t < 0 || c > best || (c == best && p < t));
 }
 
-__device__ __forceinline__ S shfl_xor_s(S x, int m) {
-  unsigned long long lo = (unsigned long long)x;
-  unsigned long long hi = (unsigned long long)((unsigned __int128)x >> 64);
-  lo = __shfl_xor(lo, m);
-  hi = __shfl_xor(hi, m);
-  return (S)(((unsigned __int128)hi << 64) | lo);
-}
-
 // Step 1 for rows of degree <= kThreadDeg (one thread per row, the row's
 // neighbour parts in this thread's LDS column).  Rows of larger degree are
 // flagged for k_gain_block; empty rows are no candidates.
@@ -127,11 +119,14 @@ __global__ __launch_bounds__(256) void k_gain_block(const int32_t *__restrict__ 
                                                     int32_t *tgt, S *gain) {
   __shared__ int32_t sp[kRefineMaxDeg];
   __shared__ int32_t cnt[kLdsParts];
-  __shared__ S rc[4], ra[4];
-  __shared__ int rt[4];
+  // per-thread candidates and own-part sums, combined by thread 0 in thread
+  // order (the combination is exact and order-free: a maximum under a total
+  // order and an integer sum)
+  __shared__ S rc[256], ra[256];
+  __shared__ int rt[256];
   constexpr bool kUnit = std::is_same_v<WT, Unit>;
   const bool table = kUnit && K <= kLdsParts;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x;
   if (table) {
     for (int k = tid; k < K; k += 256) cnt[k] = 0;
     __syncthreads();
@@ -182,27 +177,16 @@ __global__ __launch_bounds__(256) void k_gain_block(const int32_t *__restrict__ 
         }
       }
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-      const S c2 = shfl_xor_s(best, off);
-      const int t2 = __shfl_xor(t, off);
-      ca += shfl_xor_s(ca, off);
-      if (better(c2, t2, best, t)) {
-        best = c2;
-        t = t2;
-      }
-    }
-    if (lane == 0) {
-      rc[wv] = best;
-      rt[wv] = t;
-      ra[wv] = ca;
-    }
+    rc[tid] = best;
+    rt[tid] = t;
+    ra[tid] = ca;
     __syncthreads();
     if (table)   // clear the counts of this row (every read above is done)
       for (int j = tid; j < d; j += 256) cnt[sp[j]] = 0;
     if (tid == 0) {
       S B = rc[0], A = ra[0];
       int T = rt[0];
-      for (int q = 1; q < 4; ++q) {
+      for (int q = 1; q < 256; ++q) {
         A += ra[q];
         if (better(rc[q], rt[q], B, T)) {
           B = rc[q];
@@ -275,20 +259,33 @@ __global__ __launch_bounds__(256) void k_movers_wave(const int32_t *__restrict__
                                                      const int32_t *__restrict__ part,
                                                      const int32_t *__restrict__ tgt,
                                                      const S *__restrict__ gain, uint8_t *mv) {
-  const int lane = threadIdx.x & 63;
+  // lane sums through LDS, added by lane 0 in lane order; the row loop is
+  // uniform over the block (rows r0 + wave) so every wave reaches the barriers
+  __shared__ S lanes[256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nr = *nrows;
-  for (int r = (blockIdx.x * 256 + threadIdx.x) >> 6; r < nr; r += (gridDim.x * 256) >> 6) {
-    const int64_t v = rows[r];
-    const int t = tgt[v];
-    if (t < 0) {                       // wave-uniform
-      if (lane == 0) mv[v] = 0;
-      continue;
+  for (int64_t r0 = (int64_t)blockIdx.x * 4; r0 < nr; r0 += (int64_t)gridDim.x * 4) {
+    const int64_t r = r0 + wave;
+    int64_t v = -1;
+    int t = -1;
+    S g2 = 0;
+    if (r < nr) {
+      v = rows[r];
+      t = tgt[v];
+      if (t >= 0) {
+        const int64_t k0 = rp[v], k1 = rp[v + 1];
+        g2 = moved_gain<IdxT, WT>(v, k0 + lane, k1, 64, col, w, e0, part, tgt, gain, part[v],
+                                  t, gain[v]);
+      }
     }
-    const int64_t k0 = rp[v], k1 = rp[v + 1];
-    S g2 = moved_gain<IdxT, WT>(v, k0 + lane, k1, 64, col, w, e0, part, tgt, gain, part[v], t,
-                                gain[v]);
-    for (int off = 32; off >= 1; off >>= 1) g2 += shfl_xor_s(g2, off);
-    if (lane == 0) mv[v] = g2 > 0 ? 1 : 0;
+    lanes[threadIdx.x] = g2;
+    __syncthreads();
+    if (lane == 0 && v >= 0) {
+      S tot = 0;
+      for (int q = 0; q < 64; ++q) tot += lanes[wave * 64 + q];
+      mv[v] = (t >= 0 && tot > 0) ? 1 : 0;
+    }
+    __syncthreads();
   }
 }
 

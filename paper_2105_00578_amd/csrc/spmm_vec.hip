@@ -20,6 +20,8 @@
 // L h = r (Sec. 5.2).
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace sphx {
@@ -55,11 +57,28 @@ struct Csr {
   const IdxT *rp;
   const typename ColOf<WT>::type *col;
   const WT *w;
-  // neighbour of row i stored at entry k
+  // neighbour of row i stored at entry k, and the entry's weight
   __device__ __forceinline__ int64_t nbr(int64_t i, int64_t k) const {
     if constexpr (std::is_same_v<WT, UnitD16>) return i + (int64_t)col[k];
     else return (int64_t)col[k];
   }
+  __device__ __forceinline__ WT wk(int64_t k) const { return w[k]; }
+};
+
+// The same entries read from an LDS copy of a contiguous run of them
+// (entries k0 ..; staged by the row-chunk kernel below).
+template <typename WT>
+struct LdsCsr {
+  using CT = typename ColOf<WT>::type;
+  using WS = std::conditional_t<kUnitW<WT>, float, WT>;
+  const CT *col;
+  const WS *w;
+  int64_t k0;
+  __device__ __forceinline__ int64_t nbr(int64_t i, int64_t k) const {
+    if constexpr (std::is_same_v<WT, UnitD16>) return i + (int64_t)col[k - k0];
+    else return (int64_t)col[k - k0];
+  }
+  __device__ __forceinline__ WS wk(int64_t k) const { return w[k - k0]; }
 };
 
 // Block id remap: XCD x = b % 8 receives a contiguous range of block ids.
@@ -72,8 +91,8 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
 // acc = sum over entries k0, k0 + step, ... < k1 of w_k (x_i - x_col[k]).
 // U independent partial sums (U gathers in flight per lane), combined in a
 // fixed order.
-template <typename T, int VB, int NV, typename IdxT, typename WT>
-__device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t i, int64_t k0, int64_t k1,
+template <typename T, int VB, int NV, typename WT, typename Src>
+__device__ __forceinline__ void vrow_acc(const Src &A, int64_t i, int64_t k0, int64_t k1,
                                          int step, const typename Vec<T, VB>::type *__restrict__ X,
                                          int ldv, const typename Vec<T, VB>::type (&xi)[NV],
                                          typename Vec<T, VB>::type (&acc)[NV]) {
@@ -100,7 +119,7 @@ __device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t i, int6
 #pragma unroll
         for (int v = 0; v < NV; ++v) a[u][v] += xi[v] - x[u][v];
       } else {
-        const T wk = T(A.w[k + u * step]);
+        const T wk = T(A.wk(k + u * step));
 #pragma unroll
         for (int v = 0; v < NV; ++v) a[u][v] += wk * (xi[v] - x[u][v]);
       }
@@ -115,7 +134,7 @@ __device__ __forceinline__ void vrow_acc(const Csr<IdxT, WT> &A, int64_t i, int6
 #pragma unroll
         for (int v = 0; v < NV; ++v) a[u][v] += xi[v] - X[j0 * ldv + v];
       } else {
-        const T w0 = T(A.w[k]);
+        const T w0 = T(A.wk(k));
 #pragma unroll
         for (int v = 0; v < NV; ++v) a[u][v] += w0 * (xi[v] - X[j0 * ldv + v]);
       }
@@ -317,7 +336,7 @@ __global__ __launch_bounds__(256) void k_vrow(Csr<IdxT, WT> A, const int32_t *__
     V xi[NV], acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
-    vrow_acc<T, VB, NV>(A, i, (int64_t)A.rp[i], (int64_t)A.rp[i + 1], 1, X, ldv, xi, acc);
+    vrow_acc<T, VB, NV, WT>(A, i, (int64_t)A.rp[i], (int64_t)A.rp[i + 1], 1, X, ldv, xi, acc);
     epi.row(i, xi, acc, n1, n2);
   }
   if constexpr (Epi::kNorms) block_norms<LD>(n1, n2, m, partials, slot0 + (int)blockIdx.x);
@@ -355,30 +374,101 @@ __device__ __forceinline__ void group_sum(typename Vec<T, VB>::type (&acc)[NV]) 
 // indices; the group's partial sums are combined by a butterfly in a fixed
 // order and the group's first lane runs the epilogue.  rows = null: natural
 // order over all n rows.
+// rpb > 0: each block takes a contiguous range of rpb rows (a multiple of the
+// groups per block), and block ids are remapped so that each XCD works on one
+// contiguous stretch of ranges (as the one-lane kernel does): the gathered
+// neighbour rows of a mesh then stay in that XCD's L2.  rpb == 0: blocks
+// stride over the rows (the degree-binned lists of power-law graphs, whose
+// neighbours are random anyway and whose row costs vary within a bin).
 template <typename T, int VB, int NV, int G, typename IdxT, typename WT, typename Epi>
 __global__ __launch_bounds__(256) void k_vgroup(Csr<IdxT, WT> A,
                                                 const int32_t *__restrict__ rows,
                                                 int64_t nrows, const T *__restrict__ Xs,
-                                                int ld, Epi epi, double *partials, int slot0,
-                                                int m) {
+                                                int ld, int64_t rpb, Epi epi, double *partials,
+                                                int slot0, int m) {
   using V = typename Vec<T, VB>::type;
   constexpr int LD = NV * Vec<T, VB>::E;
   constexpr int GPB = 256 / G;   // groups per block
   const V *X = reinterpret_cast<const V *>(Xs);
   const int ldv = ld / Vec<T, VB>::E;
   const int gl = threadIdx.x & (G - 1);
+  const bool strided = rpb == 0;
+  const int64_t b = strided ? (int64_t)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t rend = strided ? nrows : min(nrows, (b + 1) * rpb);
+  const int64_t step = strided ? (int64_t)gridDim.x * GPB : GPB;
   double n1[LD], n2[LD];
 #pragma unroll
   for (int c = 0; c < LD; ++c) { n1[c] = 0.0; n2[c] = 0.0; }
-  for (int64_t r = (int64_t)blockIdx.x * GPB + threadIdx.x / G; r < nrows;
-       r += (int64_t)gridDim.x * GPB) {
+  for (int64_t r = (strided ? b * GPB : b * rpb) + threadIdx.x / G; r < rend; r += step) {
     const int64_t i = rows ? rows[r] : r;
     V xi[NV], acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
-    vrow_acc<T, VB, NV>(A, i, (int64_t)A.rp[i] + gl, (int64_t)A.rp[i + 1], G, X, ldv, xi, acc);
+    vrow_acc<T, VB, NV, WT>(A, i, (int64_t)A.rp[i] + gl, (int64_t)A.rp[i + 1], G, X, ldv, xi, acc);
     group_sum<T, VB, NV, G>(acc);
     if (gl == 0) epi.row(i, xi, acc, n1, n2);
+  }
+  if constexpr (Epi::kNorms) block_norms<LD>(n1, n2, m, partials, slot0 + (int)blockIdx.x);
+}
+
+// Rows of 13..48 neighbours in natural order (mesh-like graphs), G lanes per
+// row, with the column indices (and weights) staged in LDS: the block takes
+// its rows in chunks of 256 / G consecutive rows, whose CSR entries form one
+// contiguous run; the block loads that run with coalesced loads (adjacent
+// threads, adjacent entries) into LDS, and the groups then walk their rows
+// from LDS.  Read per lane from global memory instead, the index and weight
+// lines of all resident waves exceed the L2 and are fetched again (measured:
+// about twice the algorithmic bytes on the weighted 27-point mesh).  A chunk
+// with more than kLdsEntries entries is read from global memory.  Blocks take
+// contiguous chunk ranges, remapped per XCD as above.  The summation order is
+// the same as k_vgroup's.
+constexpr int kLdsEntries = 4096;
+
+template <typename T, int VB, int NV, int G, typename IdxT, typename WT, typename Epi>
+__global__ __launch_bounds__(256) void k_vlds(Csr<IdxT, WT> A, int64_t nrows,
+                                              const T *__restrict__ Xs, int ld, int64_t rpb,
+                                              Epi epi, double *partials, int slot0, int m) {
+  using V = typename Vec<T, VB>::type;
+  using L = LdsCsr<WT>;
+  constexpr int LD = NV * Vec<T, VB>::E;
+  constexpr int R = 256 / G;   // rows per chunk
+  __shared__ typename L::CT scol[kLdsEntries];
+  __shared__ typename L::WS sw[kUnitW<WT> ? 1 : kLdsEntries];
+  const V *X = reinterpret_cast<const V *>(Xs);
+  const int ldv = ld / Vec<T, VB>::E;
+  const int gl = threadIdx.x & (G - 1);
+  const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t rend = min(nrows, (b + 1) * rpb);
+  double n1[LD], n2[LD];
+#pragma unroll
+  for (int c = 0; c < LD; ++c) { n1[c] = 0.0; n2[c] = 0.0; }
+  for (int64_t r0 = b * rpb; r0 < rend; r0 += R) {
+    const int64_t r1 = min(rend, r0 + (int64_t)R);
+    const int64_t k0 = A.rp[r0], k1 = A.rp[r1];
+    const bool staged = k1 - k0 <= kLdsEntries;
+    if (staged) {
+      for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
+        scol[k - k0] = A.col[k];
+        if constexpr (!kUnitW<WT>) sw[k - k0] = A.w[k];
+      }
+    }
+    __syncthreads();
+    const int64_t i = r0 + threadIdx.x / G;
+    if (i < r1) {                       // uniform over each group of G lanes
+      V xi[NV], acc[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
+      const int64_t ka = (int64_t)A.rp[i] + gl, kb = (int64_t)A.rp[i + 1];
+      if (staged) {
+        const L S{scol, sw, k0};
+        vrow_acc<T, VB, NV, WT>(S, i, ka, kb, G, X, ldv, xi, acc);
+      } else {
+        vrow_acc<T, VB, NV, WT>(A, i, ka, kb, G, X, ldv, xi, acc);
+      }
+      group_sum<T, VB, NV, G>(acc);
+      if (gl == 0) epi.row(i, xi, acc, n1, n2);
+    }
+    __syncthreads();
   }
   if constexpr (Epi::kNorms) block_norms<LD>(n1, n2, m, partials, slot0 + (int)blockIdx.x);
 }
@@ -406,7 +496,7 @@ __global__ __launch_bounds__(256) void k_vhub_partial(
     V xi[NV], acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) xi[v] = X[i * ldv + v];
-    vrow_acc<T, VB, NV>(A, i, k0s[q] + lane, k1s[q], 64, X, ldv, xi, acc);
+    vrow_acc<T, VB, NV, WT>(A, i, k0s[q] + lane, k1s[q], 64, X, ldv, xi, acc);
     wave_sum<T, VB, NV>(acc);
     if (lane == 0)
 #pragma unroll
@@ -482,19 +572,42 @@ void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X
     used += (int)nb;
   };
   auto grouped = [&](int G, const int32_t *rows, int64_t nr, int64_t maxb) {
-    unsigned gb = grid_for(nr, 256 / G, maxb);
+    // natural order: contiguous ranges of whole group-steps per block;
+    // row lists (binned): blocks stride over the list.  At most maxb blocks.
+    const int64_t gpb = 256 / G;
+    int64_t rpb = 0;
+    unsigned gb = grid_for(nr, gpb, maxb);
+    if (!rows) {
+      const int64_t steps = ceil_div(nr, gpb);
+      rpb = ceil_div(steps, maxb) * gpb;
+      gb = (unsigned)std::max<int64_t>(1, ceil_div(nr, rpb));
+    }
     if (G == 2)
       hipExtLaunchKernelGGL((k_vgroup<T, VB, NV, 2, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
-                            e0, e1, 0, A, rows, nr, X, ld, epi, partials, used, m);
+                            e0, e1, 0, A, rows, nr, X, ld, rpb, epi, partials, used, m);
     else if (G == 4)
       hipExtLaunchKernelGGL((k_vgroup<T, VB, NV, 4, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
-                            e0, e1, 0, A, rows, nr, X, ld, epi, partials, used, m);
+                            e0, e1, 0, A, rows, nr, X, ld, rpb, epi, partials, used, m);
     else if (G == 16)
       hipExtLaunchKernelGGL((k_vgroup<T, VB, NV, 16, IdxT, WT, Epi>), dim3(gb), dim3(256), 0,
-                            s, e0, e1, 0, A, rows, nr, X, ld, epi, partials, used, m);
+                            s, e0, e1, 0, A, rows, nr, X, ld, rpb, epi, partials, used, m);
     else
       hipExtLaunchKernelGGL((k_vgroup<T, VB, NV, 64, IdxT, WT, Epi>), dim3(gb), dim3(256), 0,
-                            s, e0, e1, 0, A, rows, nr, X, ld, epi, partials, used, m);
+                            s, e0, e1, 0, A, rows, nr, X, ld, rpb, epi, partials, used, m);
+    used += (int)gb;
+  };
+  auto staged = [&](int G, int64_t nr, int64_t maxb) {
+    const int64_t R = 256 / G;
+    const int64_t chunks = ceil_div(nr, R);
+    const int64_t cpb = ceil_div(chunks, maxb);
+    const int64_t rpb = cpb * R;
+    const unsigned gb = (unsigned)std::max<int64_t>(1, ceil_div(nr, rpb));
+    if (G == 2)
+      hipExtLaunchKernelGGL((k_vlds<T, VB, NV, 2, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
+                            e0, e1, 0, A, nr, X, ld, rpb, epi, partials, used, m);
+    else
+      hipExtLaunchKernelGGL((k_vlds<T, VB, NV, 4, IdxT, WT, Epi>), dim3(gb), dim3(256), 0, s,
+                            e0, e1, 0, A, nr, X, ld, rpb, epi, partials, used, m);
     used += (int)gb;
   };
   if (!plan.binned) {
@@ -503,8 +616,14 @@ void run_vec(const Csr<IdxT, WT> &A, int64_t n, const SpmmPlan &plan, const T *X
     // lanes, FP32 and FP64), narrow rows four
     int G = plan.group;
     if (G > 1 && VB * NV >= 32) G = 2;
+    // the LDS-staged index stream pays off for the light epilogues (store,
+    // polynomial steps: 8..20 % faster on the weighted 27-point mesh); with
+    // the residual epilogue's per-thread norm sums the extra LDS costs more
+    // occupancy than it saves (measured 11..30 % slower), so that one reads
+    // its indices per lane
     if (G == 1) short_rows(nullptr, n, kMaxShortBlocks);
-    else grouped(G, nullptr, n, kGroupBlocks);
+    else if (Epi::kNorms) grouped(G, nullptr, n, kGroupBlocks);
+    else staged(G, n, kGroupBlocks);
   } else {
     for (int c = 0; c < kNumBins; ++c) {
       if (plan.nrows[c] == 0) continue;

@@ -10,8 +10,9 @@ that they agree (support for the ordering assumption of oracle.certify).
 Names: rmat22 (R-MAT scale 22 LCC, generalized, K = 16 -> d = 5),
 brick96lr (27-point 96^3 + 1 % long-range edges, weights U[0.5, 1.5),
 combinatorial, K = 256 -> d = 9), king512 (9-point 512^2, weights U[0.5, 1.5),
-generalized, d = 7) and rmat18 (R-MAT scale 18 LCC, weights U[0.5, 1.5),
-generalized, d = 7).  Runtimes on 8 host cores: minutes (king512, rmat18) to
+generalized, d = 7), rmat18 (R-MAT scale 18 LCC, weights U[0.5, 1.5),
+generalized, d = 7) and brick100 (the paper's Brick3D 27-point 100^3 mesh,
+unit weights, combinatorial, K = 24 -> d = 5).  Runtimes on 8 host cores: minutes (king512, rmat18) to
 tens of minutes (rmat22, brick96lr).
 """
 from __future__ import annotations
@@ -38,6 +39,7 @@ WORKLOADS = {
     "brick96lr": (lap.COMBINATORIAL, 9, "chebyshev"),
     "king512": (lap.GENERALIZED, 7, "chebyshev"),
     "rmat18": (lap.GENERALIZED, 7, "jacobi"),
+    "brick100": (lap.COMBINATORIAL, 5, "chebyshev"),
 }
 SEEDS = (7, 8)
 GUARDS = 4

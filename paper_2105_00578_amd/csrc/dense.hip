@@ -366,7 +366,7 @@ __device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
 __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRArgs a,
                                             double *Y, double *theta, DevStatus *st) {
   __shared__ double M1[kMaxW * LDA], M2[kMaxW * LDA], M3[kMaxW * LDA];
-  __shared__ double sc[kMaxW], lam[kMaxW], lcol[kMaxW];
+  __shared__ double sc[kMaxW], lam[kMaxW];
   __shared__ double pc[kMaxW / 2 + 1], ps[kMaxW / 2 + 1];
   __shared__ int pp[kMaxW / 2 + 1], pq[kMaxW / 2 + 1];
   __shared__ int piv[kMaxW], ipiv[kMaxW], perm[kMaxW];
@@ -423,19 +423,20 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
       __syncthreads();
       const int p = pstep;
       if (p < 0) break;
+      // column k of L (by original row) and the Schur complement on the
+      // columns not chosen yet; the pivot column of M1 is not written in this
+      // pass, so every thread reads its entries directly
+      const double rd = 1.0 / sqrt(pval);
       if (t < wl) {
-        const double d = sqrt(pval);
         double l = 0.0;
-        if (t == p) l = d;
-        else if (ipiv[t] < 0) l = M1[t * LDA + p] / d;
-        lcol[t] = l;
+        if (t == p) l = sqrt(pval);
+        else if (ipiv[t] < 0) l = M1[t * LDA + p] * rd;
         if (t == p || ipiv[t] < 0) M2[t * LDA + k] = l;
       }
-      __syncthreads();
-      // Schur complement on the columns not chosen yet
       for (int e = t; e < wl * wl; e += blockDim.x) {
         int i = e / wl, j = e - i * wl;
-        if (ipiv[i] < 0 && ipiv[j] < 0) M1[i * LDA + j] -= lcol[i] * lcol[j];
+        if (ipiv[i] < 0 && ipiv[j] < 0)
+          M1[i * LDA + j] -= (M1[i * LDA + p] * rd) * (M1[j * LDA + p] * rd);
       }
       __syncthreads();
     }
@@ -454,6 +455,8 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
         return;
       }
       // L11[i][j] = M2[piv[i]][j], lower triangular k x k.
+      // A' = L11^-1 As(piv, piv) L11^-T -> M3 (M1 as scratch)
+      auto project = [&]() {
       // T = L11^-1 As(piv, piv) -> M1, one column per thread
       if (t < k) {
         const int c = t;
@@ -483,6 +486,8 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
         }
       }
       __syncthreads();
+      };
+      project();
       // eigenpairs of A': values on the diagonal of M3, vectors in M1
       jacobi_eig(M3, M1, k, pc, ps, pp, pq, &changed);
       if (t < k) lam[t] = M3[t * LDA + t];

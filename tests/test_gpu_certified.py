@@ -30,10 +30,15 @@ from tests.gpu_util import upload
 
 pytestmark = pytest.mark.gpu
 
+# gap = None: no subspace gate.  R-MAT 22's generalized spectrum is one tight
+# cluster (theta_1..theta_8 within 0.4 %, the block edge lambda_5 - theta_4 =
+# 1.3e-5, relative 7e-5): FP32 vectors (residual floor near 1e-6 relative) can
+# reach the eigenvalue accuracy but no subspace of it is certifiable at 1e-3,
+# so angle parity is unpinned there in mixed precision.
 CASES = [
     # name, precision, K (None: eigensolve of nev), nev, precond, tol, rel, gap
-    ("rmat22", sx.FP64, 16, 5, sx.PRECOND_JACOBI, 1e-7, 1e-6, 1e-3),
-    ("rmat22", sx.MIXED, 16, 5, sx.PRECOND_JACOBI, 1e-4, 1e-4, 2e-2),
+    ("rmat22", sx.FP64, 16, 5, sx.PRECOND_JACOBI, 1e-8, 1e-6, 5e-5),
+    ("rmat22", sx.MIXED, 16, 5, sx.PRECOND_JACOBI, 1e-5, 1e-4, None),
     ("brick96lr", sx.FP64, 256, 9, sx.PRECOND_JACOBI, 1e-7, 1e-6, 5e-4),
     ("brick96lr", sx.MIXED, 256, 9, sx.PRECOND_JACOBI, 1e-5, 1e-4, 3e-2),
     ("king512", sx.FP64, None, 7, sx.PRECOND_CHEBYSHEV, 1e-8, 1e-6, 2e-3),
@@ -75,14 +80,15 @@ def test_certified_eigenpairs(handle, name, prec, K, nev, pre, tol, rel, gap):
         lam, V, part, cut, imb, st = sx.partition(handle, G, K, opts)
     Vh = V.cpu().numpy()
     err = certified.eigenvalue_errors(gold, lam)
-    blocks = certified.separated_blocks(gold, gap, kmax=nev)
+    blocks = [] if gap is None else certified.separated_blocks(gold, gap, kmax=nev)
     sins = certified.subspace_bounds(g, gold, Vh, blocks)
     print(f"\n{name} {'FP64' if prec == sx.FP64 else 'MIXED'} tol {tol}: "
           f"{st.iterations} its (promoted {st.promoted}), max rel eig err {err.max():.3e}, "
           f"blocks {blocks} sin bounds {[f'{s:.2e}' for s in sins.values()]}", flush=True)
     assert err.max() <= rel, (err, lam, gold["theta"][:nev])
-    assert blocks, "no separated block to certify"
-    assert max(sins.values()) <= 1e-3, sins
+    if gap is not None:
+        assert blocks, "no separated block to certify"
+        assert max(sins.values()) <= 1e-3, sins
     if part is not None:
         part = part.cpu().numpy()
         ref = split.split_mj(Vh[:, 1:], K) if K & (K - 1) else split.split_pow2(Vh[:, 1:], K)

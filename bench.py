@@ -54,24 +54,37 @@ METRIC = "Laplacian SpMM HBM GB/s; time to K-way eigvecs FP32 vs FP64 at equal r
 HBM_PEAK_GBS = 8000.0
 
 
+def _path_eigval(n, k):
+    """Path graph P_n: eigenvalue 2 - 2 cos(pi k / n)."""
+    import numpy as np
+    return 2.0 - 2.0 * np.cos(np.pi * k / n)
+
+
+def _grid_eigvec(side, ks):
+    """Tensor product of path eigenvectors cos(pi k (i + 1/2) / n) on the
+    side^3 grid (vertex numbering x fastest)."""
+    import numpy as np
+    i = np.arange(side)
+    v = np.ones(1)
+    for k in ks:
+        v = np.multiply.outer(v, np.cos(np.pi * k * (i + 0.5) / side))
+    return v.ravel()
+
+
 def closed_form_check(lam, V, side):
     """Eigenvalue relative errors and subspace angle against the closed-form
     spectrum of the side^3 grid (sums of path eigenvalues, tensor vectors)."""
     import numpy as np
-    from tests import closed_forms as cf
     m = len(lam)
-    exact = cf.grid_eigvals((side, side, side), m + 1)
+    ks = [(a, b, c) for a in range(3) for b in range(3) for c in range(3)]
+    val = {k: sum(_path_eigval(side, q) for q in k) for k in ks}
+    ks = sorted(ks, key=lambda k: val[k])
+    exact = np.array([val[k] for k in ks[:m + 1]])
     rel = [abs(lam[k] - exact[k]) / exact[k] for k in range(1, m)]
     trivial = abs(lam[0]) / exact[1]
     # exact invariant subspace of the m smallest (the block ends at a gap)
-    ks = []
-    for a in range(3):
-        for b in range(3):
-            for c in range(3):
-                ks.append((a, b, c))
-    val = {k: sum(cf.path_eigval(side, q) for q in k) for k in ks}
-    ks = sorted(ks, key=lambda k: val[k])[:m]
-    E = np.stack([cf.grid_eigvec((side, side, side), k) for k in ks], axis=1)
+    ks = ks[:m]
+    E = np.stack([_grid_eigvec(side, k) for k in ks], axis=1)
     # sine of the largest principal angle between span(V) and span(E)
     qv, _ = np.linalg.qr(V.astype(np.float64))
     qe, _ = np.linalg.qr(E)

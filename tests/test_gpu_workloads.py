@@ -7,7 +7,9 @@ size, computed by the oracle on the GPU's own outputs:
 * the 128^3 grid: eigenvalues and invariant subspace against the closed form;
 * the part vector equals the oracle split of the returned coordinates, and
   cut / imbalance equal the oracle's, bit for bit;
-* mixed and FP64 solves agree on the eigenvalues.
+* mixed and FP64 solves agree on the eigenvalues (a consistency check; the
+  accuracy against the oracle's certified eigenpairs of these graphs, at
+  tighter tolerances, is gated in test_gpu_certified.py).
 """
 import numpy as np
 import pytest
@@ -116,7 +118,7 @@ def test_rmat22_mixed_matches_fp64():
     assert np.allclose(a[1:], b[1:], rtol=1e-3)
 
 
-@pytest.mark.parametrize("prec", [sx.MIXED])
+@pytest.mark.parametrize("prec", [sx.MIXED, sx.FP64])
 def test_brick96_longrange_k256(handle, prec):
     """27-point 96^3 + 1% long-range edges, weights U[0.5, 1.5) FP32, K = 256."""
     g = graphgen.config_graph("brick96lr")
@@ -130,6 +132,6 @@ def test_brick96_longrange_k256(handle, prec):
     part = part.cpu().numpy()
     rq, rho, nrm = _residuals(g, sx.COMBINATORIAL, lam, V)
     assert np.allclose(nrm, 1.0, atol=1e-5) and np.allclose(rq, lam, rtol=1e-6, atol=1e-9)
-    assert rho.max() <= 1e-3 * 1.5
+    assert rho.max() <= 1e-3 * (1.5 if prec == sx.MIXED else 1.0 + 1e-6)
     _check_split_quality(g, 256, V, part, cut, imb)
     assert imb == quality.imbalance(part, 256)

@@ -165,6 +165,7 @@ template <typename T, int VB, int NV>
 struct VResidual {
   EpiResidualP<T> p;
   int m;
+  bool store_lx = true;   // false: L X is already in p.LX (streaming pass)
   static constexpr bool kNorms = true;
   using V = typename Vec<T, VB>::type;
   static constexpr int E = Vec<T, VB>::E;
@@ -191,7 +192,7 @@ struct VResidual {
           n2[c] += b * x * x;
         }
       }
-      lx[v] = acc[v];
+      if (store_lx) lx[v] = acc[v];
       out[v] = o;
     }
   }
@@ -540,6 +541,69 @@ __global__ __launch_bounds__(256) void k_vhub_combine(const int32_t *__restrict_
   if constexpr (Epi::kNorms) block_norms<LD>(n1, n2, m, partials, slot0 + (int)blockIdx.x);
 }
 
+// The residual epilogue as a streaming pass over an L X that a store product
+// has already written: one thread per row, `rpt` rows per thread in 256-row
+// strides, the same arithmetic and norm partials as the fused epilogue.
+template <typename T, int VB, int NV>
+__global__ __launch_bounds__(256) void k_resid_rows(int64_t n, const T *__restrict__ Xs,
+                                                    VResidual<T, VB, NV> epi, int rpt,
+                                                    double *partials, int m) {
+  using V = typename Vec<T, VB>::type;
+  constexpr int LD = NV * Vec<T, VB>::E;
+  const V *X = reinterpret_cast<const V *>(Xs);
+  const V *LXv = reinterpret_cast<const V *>(epi.p.LX);
+  const int ldv = epi.p.ld / Vec<T, VB>::E;
+  double n1[LD], n2[LD];
+#pragma unroll
+  for (int c = 0; c < LD; ++c) { n1[c] = 0.0; n2[c] = 0.0; }
+  for (int q = 0; q < rpt; ++q) {
+    const int64_t i = ((int64_t)blockIdx.x * rpt + q) * 256 + threadIdx.x;
+    if (i >= n) break;
+    V xi[NV], acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      xi[v] = X[i * ldv + v];
+      acc[v] = LXv[i * ldv + v];
+    }
+    epi.row(i, xi, acc, n1, n2);
+  }
+  block_norms<LD>(n1, n2, m, partials, (int)blockIdx.x);
+}
+
+template <typename T>
+int resid_stream(int64_t n, const T *X, int ld, int m, const EpiResidualP<T> &p,
+                 double *partials, int *nparts, hipStream_t s) {
+  const int64_t nb0 = ceil_div(n, 256);
+  const int rpt = (int)ceil_div(nb0, kMaxNormBlocks);
+  const unsigned nb = (unsigned)ceil_div(n, 256 * (int64_t)rpt);
+  const int row_bytes = ld * (int)sizeof(T);
+  if (row_bytes % 16) return SPHX_E_INVALID_ARG;
+#define SPHX_RS(NV_)                                                                        \
+  case NV_: {                                                                               \
+    VResidual<T, 16, NV_> e{p};                                                             \
+    e.m = m;                                                                                \
+    e.store_lx = false;                                                                     \
+    hipLaunchKernelGGL((k_resid_rows<T, 16, NV_>), dim3(nb), dim3(256), 0, s, n, X, e, rpt, \
+                       partials, m);                                                        \
+    break;                                                                                  \
+  }
+  switch (row_bytes / 16) {
+    SPHX_RS(1) SPHX_RS(2) SPHX_RS(3) SPHX_RS(4)
+    default:
+      if constexpr (std::is_same_v<T, double>) {
+        switch (row_bytes / 16) {
+          SPHX_RS(5) SPHX_RS(6) SPHX_RS(7) SPHX_RS(8)
+          default: return SPHX_E_INVALID_ARG;
+        }
+      } else {
+        return SPHX_E_INVALID_ARG;
+      }
+  }
+#undef SPHX_RS
+  if (nparts) *nparts = (int)nb;
+  return hipGetLastError() == hipSuccess ? SPHX_OK : SPHX_E_HIP;
+}
+
 // ----------------------------------------------------------------- dispatch
 constexpr int kMaxShortBlocks = 8192;
 constexpr int kGroupBlocks = 8192;
@@ -725,6 +789,16 @@ template <typename T>
 int vspmm_residual(sphx_graph *g, const SpmmPlan &plan, const T *X, int ld, int m,
                    EpiResidualP<T> epi, double *norm_partials, int *n_norm_blocks,
                    hipStream_t s) {
+  if (!plan.binned && plan.group > 1 && (ld * (int)sizeof(T)) % 16 == 0) {
+    // 13..48-neighbour meshes: the LDS-staged store product writes L X, then
+    // a streaming pass forms the residual, the Jacobi step and the norms
+    // (the fused residual epilogue keeps per-lane index reads and ran at
+    // about two thirds of the store product's rate there)
+    int r = dispatch_nv<T, VStore>(g, plan, X, ld, EpiStoreP<T>{epi.LX, ld}, m, nullptr,
+                                   nullptr, s);
+    if (r != SPHX_OK) return r;
+    return resid_stream<T>(g->n, X, ld, m, epi, norm_partials, n_norm_blocks, s);
+  }
   return dispatch_nv<T, VResidual>(g, plan, X, ld, epi, m, norm_partials, n_norm_blocks, s);
 }
 template <typename T>

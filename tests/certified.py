@@ -8,9 +8,10 @@ separation is large enough to certify a subspace (see oracle.certify).
 
 Gates for a basis V (n x d) returned by the GPU:
 * eigenvalues: lambda_i in [theta_i - eig_bound, theta_i] (the oracle's
-  certificate), so |lambda_gpu,i - lambda_i| <= |lambda_gpu,i - theta_i| +
-  eig_bound must be at most rel * theta_i (the trivial pair: at most
-  rel * theta_1);
+  certificate; where the d-block ends inside a degenerate eigenvalue and has
+  no certificate, within eps_i of theta_i by Weinstein's theorem), so
+  |lambda_gpu,i - lambda_i| <= |lambda_gpu,i - theta_i| + bound must be at
+  most rel * theta_i (the trivial pair: at most rel * theta_1);
 * subspace: for each separated leading block of k columns, the Davis-Kahan
   bound of the GPU's own residual against the certified lam_lo_k,
   sin <= ||R_k||_F / (lam_lo_k - theta_{k-1}(V)), computed in FP64 with the
@@ -52,7 +53,13 @@ def eigenvalue_errors(gold, lam):
     th = np.asarray(gold["theta"])
     lam = np.asarray(lam, dtype=np.float64)
     d = lam.size
-    err = np.abs(lam - th[:d]) + gold["eig_bound"]
+    # the block's quadratic bound when the block is separated; otherwise
+    # (block edge inside a degenerate eigenvalue) each value's Weinstein
+    # radius eps_i, which is first order but still far below the targets
+    bound = gold["eig_bound"]
+    if not np.isfinite(bound):
+        bound = np.asarray(gold["eps"])[:d]
+    err = np.abs(lam - th[:d]) + bound
     scale = th[:d].copy()
     scale[0] = th[1]
     return err / scale

@@ -588,7 +588,7 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   UpdateArgs ua{n, m, ld, idm, 0, 0};
   ua.act.count = 0;
   tid = pl.begin(PH_UPDATE, 0.0, s);
-  SPHX_TRY(launch_update<T>(w.X, nullptr, w.P, nullptr, w.LP, w.Y, ua, s));
+  SPHX_TRY(launch_update<T>(w.X, nullptr, w.P, nullptr, nullptr, w.Y, ua, s));
   pl.end(tid, s);
   const bool jac = o.precond == SPHX_PRECOND_JACOBI;
   auto residual = [&]() -> int {
@@ -654,8 +654,20 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     pl.end(tid, s);
     UpdateArgs ub{n, m, ld, act, 1, have_p ? 1 : 0};
     tid = pl.begin(PH_UPDATE, 0.0, s);
-    SPHX_TRY(launch_update<T>(w.X, H, w.P, w.LH, w.LP, w.Y, ub, s));
+    // FP64 carries L P along as L H y + L P z.  FP32 forms it by a product:
+    // the combination keeps the absolute rounding of the stored FP32 products
+    // of earlier steps while P shrinks, and once P is rescaled in the
+    // Rayleigh-Ritz step that error dominates its projected entries (converged
+    // columns then diverged near the tolerance)
+    constexpr bool lp_product = std::is_same_v<T, float>;
+    SPHX_TRY(launch_update<T>(w.X, H, w.P, w.LH, lp_product ? nullptr : w.LP, w.Y, ub, s));
     pl.end(tid, s);
+    if (lp_product) {
+      tid = pl.begin(PH_SPMM, spmm_bytes(G, w.plan, m, vs, 2, 0), s);
+      SPHX_TRY(vspmm_store<T>(G, w.plan, w.P, ld, m, EpiStoreP<T>{w.LP, ld}, s));
+      pl.end(tid, s);
+      ++calls;
+    }
     have_p = true;
     // Jacobi writes the next H into B1, which held this iteration's H (consumed
     // by the update above); Chebyshev and no preconditioner write R.

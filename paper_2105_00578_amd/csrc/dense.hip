@@ -256,20 +256,93 @@ constexpr int LDA = kMaxW + 1;
 static_assert(kMaxW < 64, "Rayleigh-Ritz pivot search: one candidate per lane of a wave");
 
 // Cyclic Jacobi eigensolver (round-robin parallel ordering) on the k x k
-// symmetric matrix A (LDS, stride LDA); V receives the eigenvectors.  The
-// pairs of one round are disjoint, so A <- R^T A R splits into independent
-// 2 x 2 blocks (pair I's rows, pair J's columns): each thread takes one block,
-// rotates its rows with pair I's angle, then its columns with pair J's (the
-// same operations, in the same order, as a row pass followed by a column
-// pass), and V <- V R likewise by blocks.  One barrier after the angles and
-// one after the update per round.
-__device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
-                           int *pp, int *pq, int *changed) {
+// symmetric matrix in A (LDS, stride LDA); V receives the eigenvectors, and
+// the returned pointer (A or B) the rotated matrix.  For odd k the matrices
+// carry one zero row and column k (its pairs never rotate), so that every
+// pair of a round has two rows.  The pairs of one round are disjoint, so
+// A <- R^T A R splits into independent 2 x 2 blocks (pair I's rows, pair J's
+// columns).  In every wave, lane I computes the angle of pair I from the
+// matrix of the previous round; each thread then takes one block, fetches
+// the angles of I and J from those lanes, rotates its rows with I's angle,
+// then its columns with J's (a row pass followed by a column pass; a pair
+// that does not rotate has c = 1, s = 0, which leaves its entries exactly as
+// they are), and writes the block into the other buffer; V <- V R likewise
+// by blocks, in place.  One barrier per round.  Before each sweep every pair
+// is tested once: the sweeps stop when no pair would rotate.
+__device__ __forceinline__ void jacobi_pair(int r, int t, int kk, int &p, int &q) {
+  if (t == 0) {
+    p = kk - 1;
+    q = r;
+  } else {
+    p = r + t;
+    if (p >= kk - 1) p -= kk - 1;
+    q = r - t;
+    if (q < 0) q += kk - 1;
+  }
+  if (p > q) {
+    const int tmp = p;
+    p = q;
+    q = tmp;
+  }
+}
+
+// rotations stop once an off-diagonal entry is at rounding level (a few ulps
+// of ||A||), or negligible next to both diagonal entries:
+// |a_pq| > 2e-16 sqrt(|a_pp a_qq|), compared in squares
+__device__ __forceinline__ bool jacobi_rotates(double apq, double app, double aqq,
+                                               double abs_floor) {
+  return fabs(apq) > abs_floor && apq * apq > 4e-32 * fabs(app * aqq);
+}
+
+// 1/x and 1/sqrt(x) from the hardware estimates and two Newton steps each
+// (quadratic convergence from the estimate's error to a few ulps)
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  for (int i = 0; i < 2; ++i) {
+    const double h = fma(-0.5 * x * y, y, 0.5);   // (1 - x y^2) / 2
+    y = fma(y, h, y);
+  }
+  return y;
+}
+
+// Rotation (c, s) that annihilates a_pq (Rutishauser's form: the tangent
+// t = sgn(th) / (|th| + sqrt(th^2 + 1)), th = (a_qq - a_pp) / (2 a_pq), the
+// smaller root; c = 1 / sqrt(1 + t^2), s = t c); (1, 0) if the pair does not
+// rotate.  th is clamped at 1e150 (then t ~ 1 / (2 th) underflows to a
+// negligible rotation either way).
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, bool rot,
+                                                double &c, double &s) {
+  const double h = rot ? 2.0 * apq : 1.0;
+  double th = (aqq - app) * recip(h);
+  th = fmin(fmax(th, -1e150), 1e150);
+  const double q = fma(th, th, 1.0);
+  const double sq = q * rsqrt_nr(q);
+  const double tt = (th >= 0 ? 1.0 : -1.0) * recip(fabs(th) + sq);
+  const double cc = rsqrt_nr(fma(tt, tt, 1.0));
+  c = rot ? cc : 1.0;
+  s = rot ? tt * cc : 0.0;
+}
+
+constexpr int kJacobiThreads = 256;
+// blocks per thread and round: 2 (kMaxW / 2)^2 over kJacobiThreads threads
+constexpr int kJacobiItems = (2 * (kMaxW / 2) * (kMaxW / 2) + kJacobiThreads - 1) / kJacobiThreads;
+
+__device__ double *jacobi_eig(double *A, double *B, double *V, int k, int *flags) {
   __shared__ double anorm;
   const int t = threadIdx.x;
-  for (int e = t; e < k * k; e += blockDim.x) {
-    int i = e / k, j = e - i * k;
+  const int lane = t & 63;
+  const int kk = k + (k & 1);
+  for (int e = t; e < kk * kk; e += blockDim.x) {
+    const int i = e / kk, j = e - i * kk;
     V[i * LDA + j] = (i == j) ? 1.0 : 0.0;
+    if (i == k || j == k) A[i * LDA + j] = 0.0;   // odd k: the zero row and column
   }
   if (t < 64) {
     double s = 0.0;
@@ -280,76 +353,92 @@ __device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
     if (t == 0) anorm = sqrt(s);
   }
+  if (t < 3) flags[t] = 0;
   __syncthreads();
-  if (k < 2) return;
-  // rotations stop once off-diagonal entries are at rounding level (a few
-  // ulps of ||A||), or negligible next to both diagonal entries
+  if (k < 2) return A;
   const double abs_floor = 4e-16 * anorm + 1e-300;
-  const int kk = k + (k & 1);
-  const int npair = kk / 2;
+  const int npair = kk / 2;              // <= kMaxW / 2 < 64: one pair per lane
   const int nblk = npair * npair;
+  const int nwork = 2 * nblk;
+  const int npq = k * (k - 1) / 2;
+  // this thread's blocks (fixed over the rounds): pair indices and kind
+  int bI[kJacobiItems], bJ[kJacobiItems];
+  bool bV[kJacobiItems], bOk[kJacobiItems];
+#pragma unroll
+  for (int u = 0; u < kJacobiItems; ++u) {
+    const int e = t + u * kJacobiThreads;
+    bOk[u] = e < nwork;
+    bV[u] = e >= nblk;
+    const int b = e < nblk ? e : (e < nwork ? e - nblk : 0);
+    bI[u] = b / npair;
+    bJ[u] = b - bI[u] * npair;
+  }
+  double *cur = A, *nxt = B;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (t == 0) *changed = 0;
+    // flags cycle through three words: the one tested now was cleared two
+    // sweeps ago, and read by every thread before the barriers of the last
+    // sweep, when it is cleared again
+    int *rot = flags + sweep % 3;
+    if (t == 0) flags[(sweep + 1) % 3] = 0;
+    for (int e = t; e < npq; e += blockDim.x) {
+      // pair (p, q), p < q: e = q (q - 1) / 2 + p
+      int q = (int)((1.0 + sqrt(1.0 + 8.0 * e)) * 0.5);
+      while (q * (q - 1) / 2 > e) --q;
+      while ((q + 1) * q / 2 <= e) ++q;
+      const int p = e - q * (q - 1) / 2;
+      if (jacobi_rotates(cur[p * LDA + q], cur[p * LDA + p], cur[q * LDA + q], abs_floor))
+        *rot = 1;
+    }
     __syncthreads();
+    if (*rot == 0) break;
     for (int r = 0; r < kk - 1; ++r) {
-      if (t < npair) {
+      double c, s;
+      {
         int p, q;
-        if (t == 0) { p = kk - 1; q = r; }
-        else { p = (r + t) % (kk - 1); q = (r - t + kk - 1) % (kk - 1); }
-        if (p > q) { int tmp = p; p = q; q = tmp; }
-        double c = 1.0, s = 0.0;
-        if (q < k) {
-          double apq = A[p * LDA + q];
-          double app = A[p * LDA + p], aqq = A[q * LDA + q];
-          if (fabs(apq) > abs_floor && fabs(apq) > 2e-16 * sqrt(fabs(app * aqq))) {
-            double th = (aqq - app) / (2.0 * apq);
-            double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(tt * tt + 1.0);
-            s = tt * c;
-            *changed = 1;
-          }
-        }
-        pp[t] = p; pq[t] = q; pc[t] = c; ps[t] = s;
+        jacobi_pair(r, lane < npair ? lane : 0, kk, p, q);
+        const double apq = cur[p * LDA + q];
+        const double app = cur[p * LDA + p], aqq = cur[q * LDA + q];
+        const bool rr = lane < npair && q < k && jacobi_rotates(apq, app, aqq, abs_floor);
+        jacobi_rotation(app, aqq, apq, rr, c, s);
       }
-      __syncthreads();
-      // blocks of A (e < nblk) and of V (nblk <= e < 2 nblk); a pair whose
-      // second index is k (odd k) has no rotation and only its first row
-      for (int e = t; e < 2 * nblk; e += blockDim.x) {
-        const bool isv = e >= nblk;
-        const int b = isv ? e - nblk : e;
-        const int I = b / npair, J = b - I * npair;
-        const double sI = isv ? 0.0 : ps[I], sJ = ps[J];
-        if (sI == 0.0 && sJ == 0.0) continue;
-        double *M = isv ? V : A;
-        const int p0 = pp[I], q0 = pq[I], p1 = pp[J], q1 = pq[J];
-        const bool r1 = q0 < k, c1 = q1 < k;
-        double a00 = M[p0 * LDA + p1];
-        double a01 = c1 ? M[p0 * LDA + q1] : 0.0;
-        double a10 = r1 ? M[q0 * LDA + p1] : 0.0;
-        double a11 = (r1 && c1) ? M[q0 * LDA + q1] : 0.0;
-        if (sI != 0.0) {
-          const double cI = pc[I];
+#pragma unroll
+      for (int u = 0; u < kJacobiItems; ++u) {
+        if (u * kJacobiThreads >= nwork) break;     // uniform
+        const int I = bI[u], J = bJ[u];
+        const double cI0 = __shfl(c, I), sI0 = __shfl(s, I);
+        const double cJ = __shfl(c, J), sJ = __shfl(s, J);
+        if (!bOk[u]) continue;
+        const bool isv = bV[u];
+        const double cI = isv ? 1.0 : cI0, sI = isv ? 0.0 : sI0;
+        int p0, q0, p1, q1;
+        jacobi_pair(r, I, kk, p0, q0);
+        jacobi_pair(r, J, kk, p1, q1);
+        const double *M = isv ? V : cur;
+        double *O = isv ? V : nxt;
+        double a00 = M[p0 * LDA + p1], a01 = M[p0 * LDA + q1];
+        double a10 = M[q0 * LDA + p1], a11 = M[q0 * LDA + q1];
+        {
           const double b00 = cI * a00 - sI * a10, b10 = sI * a00 + cI * a10;
           const double b01 = cI * a01 - sI * a11, b11 = sI * a01 + cI * a11;
           a00 = b00; a10 = b10; a01 = b01; a11 = b11;
         }
-        if (sJ != 0.0) {
-          const double cJ = pc[J];
+        {
           const double b00 = cJ * a00 - sJ * a01, b01 = sJ * a00 + cJ * a01;
           const double b10 = cJ * a10 - sJ * a11, b11 = sJ * a10 + cJ * a11;
           a00 = b00; a01 = b01; a10 = b10; a11 = b11;
         }
-        M[p0 * LDA + p1] = a00;
-        if (c1) M[p0 * LDA + q1] = a01;
-        if (r1) M[q0 * LDA + p1] = a10;
-        if (r1 && c1) M[q0 * LDA + q1] = a11;
+        O[p0 * LDA + p1] = a00;
+        O[p0 * LDA + q1] = a01;
+        O[q0 * LDA + p1] = a10;
+        O[q0 * LDA + q1] = a11;
       }
       __syncthreads();
+      double *tmp = cur;
+      cur = nxt;
+      nxt = tmp;
     }
-    if (*changed == 0) break;
-    __syncthreads();
   }
-  __syncthreads();
+  return cur;
 }
 
 // Rayleigh-Ritz (Algorithm 1, RR(S, nev)) on the reduced Gram matrices.
@@ -359,20 +448,25 @@ __device__ void jacobi_eig(double *A, double *V, int k, double *pc, double *ps,
 // step, the column with the largest remaining Schur-complement diagonal and
 // stops when that is at most drop_tol: the k chosen columns span the others
 // up to the tolerance (those are dropped as linearly dependent), and
-// Gs(piv, piv) = L L^T.  With C = L^-T, S(:, piv) C is B-orthonormal and the
-// projected matrix A' = L^-1 As(piv, piv) L^-T is diagonalised by cyclic
-// Jacobi; the m smallest Ritz pairs give Y = D P L^-T Z.  If fewer than m
+// Gs(piv, piv) = L L^T.  The rows of W = L^-1 are formed along with the
+// columns of L: row k is W[k][c] = -(1 / l_kk) sum_j L[k][j] W[j][c] for
+// c < k and 1 / l_kk for c = k, where the sums are accumulated step by step
+// for every row not chosen yet (acc[i][c] += l_ik W[k][c], right-looking),
+// so L itself is never stored.  With C = W^T, S(:, piv) C is B-orthonormal
+// and the projected matrix A' = W As(piv, piv) W^T is diagonalised by cyclic
+// Jacobi; the m smallest Ritz pairs give Y = D P W^T Z.  If fewer than m
 // columns survive, the P block is dropped and the step retried once.
-__global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRArgs a,
-                                            double *Y, double *theta, DevStatus *st) {
-  __shared__ double M1[kMaxW * LDA], M2[kMaxW * LDA], M3[kMaxW * LDA];
-  __shared__ double sc[kMaxW], lam[kMaxW];
-  __shared__ double pc[kMaxW / 2 + 1], ps[kMaxW / 2 + 1];
-  __shared__ int pp[kMaxW / 2 + 1], pq[kMaxW / 2 + 1];
+constexpr int kRRThreads = kJacobiThreads;
+constexpr int kRRItems = (kMaxW * kMaxW + kRRThreads - 1) / kRRThreads;
+
+__global__ __launch_bounds__(kRRThreads) void k_rr(const double *__restrict__ gram, RRArgs a,
+                                                   double *Y, double *theta, DevStatus *st) {
+  __shared__ double M1[kMaxW * LDA], M2[kMaxW * LDA], M3[kMaxW * LDA], Wi[kMaxW * LDA];
+  __shared__ double sc[kMaxW], lam[kMaxW], dg[2][kMaxW];
   __shared__ int piv[kMaxW], ipiv[kMaxW], perm[kMaxW];
-  __shared__ int changed, pstep;
-  __shared__ double pval;
+  __shared__ int flags[3];
   const int t = threadIdx.x;
+  const int lane = t & 63;
   const int w = a.w, m = a.m;
   const double *GA = gram;
   const double *GB = gram + kMaxW * kMaxW;
@@ -385,58 +479,84 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
       ipiv[t] = -1;
     }
     __syncthreads();
-    // M1 = Gs (then its Schur complements), M3 = As, M2 = L by original row
+    // M1 = Gs (then its Schur complements, diagonal also in dg), M3 = As,
+    // M2 = the accumulated sums acc[i][c] of the rows of W; after the
+    // factorisation M1, M2 and M3 take As(piv, piv), As(piv, piv) W^T and A'
+    // in turn
     for (int e = t; e < wl * wl; e += blockDim.x) {
       int i = e / wl, j = e - i * wl;
       int lo = i < j ? i : j, hi = i < j ? j : i;
       double sij = sc[i] * sc[j];
-      M1[i * LDA + j] = GB[lo * kMaxW + hi] * sij;
+      const double gs = GB[lo * kMaxW + hi] * sij;
+      M1[i * LDA + j] = gs;
+      if (i == j) dg[0][i] = gs;
       M3[i * LDA + j] = GA[lo * kMaxW + hi] * sij;
       M2[i * LDA + j] = 0.0;
     }
+    // this thread's entries (i, j) of the wl x wl matrices, fixed over the
+    // steps, and whether row i / column j has been chosen (the same for every
+    // thread: the pivots are)
+    int ei[kRRItems], ej[kRRItems];
+    bool ci[kRRItems], cj[kRRItems];
+#pragma unroll
+    for (int u = 0; u < kRRItems; ++u) {
+      const int e = t + u * kRRThreads;
+      const bool ok = e < wl * wl;
+      ei[u] = ok ? e / wl : 0;
+      ej[u] = ok ? e - ei[u] * wl : 0;
+      ci[u] = !ok;                 // nothing to do for entries past the matrix
+      cj[u] = false;
+    }
+    bool ct = t >= wl;             // column t chosen (or past the matrix)
     __syncthreads();
-    // ---- pivoted Cholesky of Gs
+    // ---- pivoted Cholesky of Gs, one barrier per step: every wave finds
+    // the pivot itself from the diagonal of the previous step (dg[k & 1],
+    // which this step does not write; chosen columns hold 0 there)
     int k = 0;
     for (; k < wl; ++k) {
-      if (t < 64) {
-        // pivot: the largest positive remaining diagonal entry, the lowest
-        // index on ties (wave 0, one candidate per lane: wl <= kMaxW < 64)
-        double bv = (t < wl && ipiv[t] < 0) ? M1[t * LDA + t] : 0.0;
-        int best = bv > 0.0 ? t : -1;
-        for (int off = 32; off >= 1; off >>= 1) {
-          const double ov = __shfl_xor(bv, off);
-          const int ob = __shfl_xor(best, off);
-          if (ob >= 0 && (best < 0 || ov > bv || (ov == bv && ob < best))) {
-            bv = ov;
-            best = ob;
-          }
-        }
-        if (t == 0) {
-          pstep = (best >= 0 && bv > a.drop_tol) ? best : -1;
-          pval = bv;
-          if (pstep >= 0) {
-            piv[k] = best;
-            ipiv[best] = k;
-          }
+      // the largest positive remaining diagonal entry, the lowest index on
+      // ties (one candidate per lane: wl <= kMaxW < 64)
+      double bv = lane < wl ? dg[k & 1][lane] : 0.0;
+      int best = bv > 0.0 ? lane : -1;
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int ob = __shfl_xor(best, off);
+        if (ob >= 0 && (best < 0 || ov > bv || (ov == bv && ob < best))) {
+          bv = ov;
+          best = ob;
         }
       }
-      __syncthreads();
-      const int p = pstep;
+      const int p = (best >= 0 && bv > a.drop_tol) ? best : -1;
       if (p < 0) break;
-      // column k of L (by original row) and the Schur complement on the
-      // columns not chosen yet; the pivot column of M1 is not written in this
-      // pass, so every thread reads its entries directly
+      const double pval = bv;
       const double rd = 1.0 / sqrt(pval);
-      if (t < wl) {
-        double l = 0.0;
-        if (t == p) l = sqrt(pval);
-        else if (ipiv[t] < 0) l = M1[t * LDA + p] * rd;
-        if (t == p || ipiv[t] < 0) M2[t * LDA + k] = l;
+      if (t == 0) {
+        piv[k] = p;
+        ipiv[p] = k;
       }
-      for (int e = t; e < wl * wl; e += blockDim.x) {
-        int i = e / wl, j = e - i * wl;
-        if (ipiv[i] < 0 && ipiv[j] < 0)
-          M1[i * LDA + j] -= (M1[i * LDA + p] * rd) * (M1[j * LDA + p] * rd);
+      // row k of W
+      if (t <= k) Wi[k * LDA + t] = t == k ? rd : -rd * M2[p * LDA + t];
+      // chosen columns leave the diagonal search
+      if (t == p) ct = true;
+      if (t < wl && ct) dg[(k + 1) & 1][t] = 0.0;
+      // Schur complement on the columns not chosen yet, and the sums of the
+      // rows of W not formed yet (column p of M1 and row p of M2 are not
+      // written in this step); all loads of an entry are issued first
+#pragma unroll
+      for (int u = 0; u < kRRItems; ++u) {
+        const int i = ei[u], j = ej[u];
+        if (i == p) ci[u] = true;
+        if (j == p) cj[u] = true;
+        if (ci[u]) continue;
+        const double mip = M1[i * LDA + p], mjp = M1[j * LDA + p], mij = M1[i * LDA + j];
+        const double apj = M2[p * LDA + j], aij = M2[i * LDA + j];
+        const double li = mip * rd;
+        if (!cj[u]) {
+          const double v = mij - li * (mjp * rd);
+          M1[i * LDA + j] = v;
+          if (i == j) dg[(k + 1) & 1][i] = v;
+        }
+        if (j <= k) M2[i * LDA + j] = aij + li * (j == k ? rd : -rd * apj);
       }
       __syncthreads();
     }
@@ -454,43 +574,43 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
         }
         return;
       }
-      // L11[i][j] = M2[piv[i]][j], lower triangular k x k.
-      // A' = L11^-1 As(piv, piv) L11^-T -> M3 (M1 as scratch)
-      auto project = [&]() {
-      // T = L11^-1 As(piv, piv) -> M1, one column per thread
-      if (t < k) {
-        const int c = t;
-        for (int i = 0; i < k; ++i) {
-          double v = M3[piv[i] * LDA + piv[c]];
-          for (int j = 0; j < i; ++j) v -= M2[piv[i] * LDA + j] * M1[j * LDA + c];
-          M1[i * LDA + c] = v / M2[piv[i] * LDA + i];
-        }
-      }
-      __syncthreads();
-      // A' = L11^-1 T^T -> M3: column c has right-hand side row c of T
-      if (t < k) {
-        const int c = t;
-        for (int i = 0; i < k; ++i) {
-          double v = M1[c * LDA + i];
-          for (int j = 0; j < i; ++j) v -= M2[piv[i] * LDA + j] * M3[j * LDA + c];
-          M3[i * LDA + c] = v / M2[piv[i] * LDA + i];
-        }
-      }
-      __syncthreads();
+      // Ap = As(piv, piv) -> M1
       for (int e = t; e < k * k; e += blockDim.x) {
-        int i = e / k, j = e - i * k;
-        if (i < j) {
-          double v = 0.5 * (M3[i * LDA + j] + M3[j * LDA + i]);
-          M3[i * LDA + j] = v;
-          M3[j * LDA + i] = v;
-        }
+        const int i = e / k, j = e - i * k;
+        M1[i * LDA + j] = M3[piv[i] * LDA + piv[j]];
       }
       __syncthreads();
-      };
-      project();
-      // eigenpairs of A': values on the diagonal of M3, vectors in M1
-      jacobi_eig(M3, M1, k, pc, ps, pp, pq, &changed);
-      if (t < k) lam[t] = M3[t * LDA + t];
+      // T = Ap W^T -> M2 (W lower triangular: j <= c)
+      for (int e = t; e < k * k; e += blockDim.x) {
+        const int i = e / k, c = e - i * k;
+        double s0 = 0.0, s1 = 0.0;
+        int j = 0;
+        for (; j + 1 <= c; j += 2) {
+          s0 += M1[i * LDA + j] * Wi[c * LDA + j];
+          s1 += M1[i * LDA + j + 1] * Wi[c * LDA + j + 1];
+        }
+        if (j <= c) s0 += M1[i * LDA + j] * Wi[c * LDA + j];
+        M2[i * LDA + c] = s0 + s1;
+      }
+      __syncthreads();
+      // A' = W T -> M3 (j <= i), upper triangle computed and mirrored
+      for (int e = t; e < k * k; e += blockDim.x) {
+        const int i = e / k, c = e - i * k;
+        if (i > c) continue;
+        double s0 = 0.0, s1 = 0.0;
+        int j = 0;
+        for (; j + 1 <= i; j += 2) {
+          s0 += Wi[i * LDA + j] * M2[j * LDA + c];
+          s1 += Wi[i * LDA + j + 1] * M2[(j + 1) * LDA + c];
+        }
+        if (j <= i) s0 += Wi[i * LDA + j] * M2[j * LDA + c];
+        M3[i * LDA + c] = s0 + s1;
+        M3[c * LDA + i] = s0 + s1;
+      }
+      __syncthreads();
+      // eigenpairs of A': values on the diagonal, vectors in M2
+      const double *Af = jacobi_eig(M3, M1, M2, k, flags);
+      if (t < k) lam[t] = Af[t * LDA + t];
       __syncthreads();
       if (t < k) {
         int rank = 0;
@@ -500,21 +620,22 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
         perm[rank] = t;
       }
       __syncthreads();
-      // y_c = L11^-T z_perm[c] -> M3 columns (back substitution per column)
-      if (t < m) {
-        const int c = t, zc = perm[c];
-        for (int i = k - 1; i >= 0; --i) {
-          double v = M1[i * LDA + zc];
-          for (int j = i + 1; j < k; ++j) v -= M2[piv[j] * LDA + i] * M3[j * LDA + c];
-          M3[i * LDA + c] = v / M2[piv[i] * LDA + i];
-        }
-      }
-      __syncthreads();
-      // Y (basis row i, Ritz vector c) = sc_i * y_c[position of i], 0 if dropped
+      // Y (basis row i, Ritz vector c) = sc_i (W^T z_perm[c])[position of
+      // i], 0 if dropped
       for (int e = t; e < kMaxW * kMaxNev; e += blockDim.x) {
         int i = e / kMaxNev, c = e - i * kMaxNev;
         double v = 0.0;
-        if (i < wl && c < m && ipiv[i] >= 0) v = sc[i] * M3[ipiv[i] * LDA + c];
+        if (i < wl && c < m && ipiv[i] >= 0) {
+          const int r = ipiv[i], zc = perm[c];
+          double s0 = 0.0, s1 = 0.0;
+          int j = r;
+          for (; j + 1 < k; j += 2) {
+            s0 += Wi[j * LDA + r] * M2[j * LDA + zc];
+            s1 += Wi[(j + 1) * LDA + r] * M2[(j + 1) * LDA + zc];
+          }
+          if (j < k) s0 += Wi[j * LDA + r] * M2[j * LDA + zc];
+          v = sc[i] * (s0 + s1);
+        }
         Y[e] = v;
       }
       if (t < m) theta[t] = lam[perm[t]];
@@ -538,13 +659,11 @@ __global__ __launch_bounds__(256) void k_rr(const double *__restrict__ gram, RRA
 // Jacobi.  The roots are written in modified Leja order: the largest first,
 // then each maximising the sum of log distances to those already chosen
 // (lowest index on ties).  status: 0, or 1 if H_k is not positive definite.
-__global__ __launch_bounds__(256) void k_harmonic_ritz(const double *__restrict__ Hg, int k1,
+__global__ __launch_bounds__(kJacobiThreads) void k_harmonic_ritz(const double *__restrict__ Hg, int k1,
                                                        double *theta, int *status) {
   __shared__ double Mk[kMaxW * LDA], Mc[kMaxW * LDA], Mv[kMaxW * LDA];
   __shared__ double lam[kMaxW];
-  __shared__ double pc[kMaxW / 2 + 1], ps[kMaxW / 2 + 1];
-  __shared__ int pp[kMaxW / 2 + 1], pq[kMaxW / 2 + 1];
-  __shared__ int changed, bad;
+  __shared__ int flags[3], bad;
   const int t = threadIdx.x;
   // Mk = sym(H_k), Mc = H^T H
   for (int e = t; e < k1 * k1; e += blockDim.x) {
@@ -603,8 +722,9 @@ __global__ __launch_bounds__(256) void k_harmonic_ritz(const double *__restrict_
     }
   }
   __syncthreads();
-  jacobi_eig(Mc, Mv, k1, pc, ps, pp, pq, &changed);
-  if (t < k1) lam[t] = Mc[t * LDA + t];
+  // Mk (the factor) is free now: the second buffer of the rotations
+  const double *Af = jacobi_eig(Mc, Mk, Mv, k1, flags);
+  if (t < k1) lam[t] = Af[t * LDA + t];
   __syncthreads();
   if (t == 0) {
     bool used[kMaxW];
@@ -640,6 +760,7 @@ struct UpdDev {
   int act[kMaxNev];
   int use_h, use_p;
   int offH, offP;     // rows of Y for the H and P parts
+  int update_lp;      // also LP <- LH y_H + LP y_P
 };
 
 // Rows of all blocks have stride ld, a multiple of E (4 floats: 16-byte
@@ -674,6 +795,7 @@ __global__ __launch_bounds__(256) void k_update(T *X, const T *__restrict__ H, T
   const T *lP = reinterpret_cast<const T *>(sP);
   const T *lLH = reinterpret_cast<const T *>(sLH);
   const T *lLP = reinterpret_cast<const T *>(sLP);
+  const bool upd_lp = a.update_lp;
   const int m = a.m, ld = a.ld;
   const int rc = CH / ld;       // rows per chunk
   const int t = threadIdx.x;
@@ -688,11 +810,11 @@ __global__ __launch_bounds__(256) void k_update(T *X, const T *__restrict__ H, T
       sX[t] = reinterpret_cast<const V *>(X)[vb];
       if (a.use_h) {
         sH[t] = reinterpret_cast<const V *>(H)[vb];
-        sLH[t] = reinterpret_cast<const V *>(LH)[vb];
+        if (upd_lp) sLH[t] = reinterpret_cast<const V *>(LH)[vb];
       }
       if (a.use_p) {
         sP[t] = reinterpret_cast<const V *>(P)[vb];
-        sLP[t] = reinterpret_cast<const V *>(LP)[vb];
+        if (upd_lp) sLP[t] = reinterpret_cast<const V *>(LP)[vb];
       }
     }
     __syncthreads();
@@ -707,22 +829,22 @@ __global__ __launch_bounds__(256) void k_update(T *X, const T *__restrict__ H, T
       const int o = row * ld;
       if (a.use_h)
         for (int q = 0; q < a.na; ++q) {
-          double y = sY[(a.offH + q) * kMaxNev + c];
+          const double y = sY[(a.offH + q) * kMaxNev + c];
           p += double(lH[o + a.act[q]]) * y;
-          lp += double(lLH[o + a.act[q]]) * y;
+          if (upd_lp) lp += double(lLH[o + a.act[q]]) * y;
         }
       if (a.use_p)
         for (int q = 0; q < a.na; ++q) {
-          double y = sY[(a.offP + q) * kMaxNev + c];
+          const double y = sY[(a.offP + q) * kMaxNev + c];
           p += double(lP[o + a.act[q]]) * y;
-          lp += double(lLP[o + a.act[q]]) * y;
+          if (upd_lp) lp += double(lLP[o + a.act[q]]) * y;
         }
       for (int k = 0; k < m; ++k) x += double(lX[o + k]) * sY[k * kMaxNev + c];
       x += p;
       X[base + e] = T(x);
       if (write_p) {
         P[base + e] = T(p);
-        LP[base + e] = T(lp);
+        if (upd_lp) LP[base + e] = T(lp);
       }
     }
   }
@@ -1000,12 +1122,12 @@ int gram(const T *X, const T *LX, const T *H, const T *LH, const T *P, const T *
 
 void launch_harmonic_ritz(const double *H, int k1, double *theta, int *status,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_harmonic_ritz, dim3(1), dim3(256), 0, s, H, k1, theta, status);
+  hipLaunchKernelGGL(k_harmonic_ritz, dim3(1), dim3(kJacobiThreads), 0, s, H, k1, theta, status);
 }
 
 void launch_rr(const double *gram_out, const RRArgs &a, double *Y, double *theta,
                DevStatus *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_rr, dim3(1), dim3(256), 0, s, gram_out, a, Y, theta, st);
+  hipLaunchKernelGGL(k_rr, dim3(1), dim3(kRRThreads), 0, s, gram_out, a, Y, theta, st);
 }
 
 template <typename T>
@@ -1021,6 +1143,7 @@ int launch_update(T *X, const T *H, T *P, const T *LH, T *LP, const double *Y,
   d.use_p = a.use_p && d.na > 0;
   d.offH = a.m;
   d.offP = a.m + (d.use_h ? d.na : 0);
+  d.update_lp = LP != nullptr && (d.use_h || d.use_p);
   // rows of whole load vectors (the solver pads every block to 16 bytes)
   constexpr int E = UpdVec<T>::E;
   if (a.ld % E != 0 || a.ld > 256 || a.m > a.ld) return SPHX_E_INVALID_ARG;

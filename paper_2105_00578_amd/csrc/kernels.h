@@ -221,7 +221,8 @@ struct UpdateArgs {
   int use_h, use_p;
 };
 // SPHX_E_INVALID_ARG unless ld is at most 256, at least m and, for FP32, a
-// multiple of 4.
+// multiple of 4.  With LP non-null, LP is updated along with P from LH and
+// LP (otherwise the caller forms L P by a product).
 template <typename T>
 int launch_update(T *X, const T *H, T *P, const T *LH, T *LP, const double *Y,
                   const UpdateArgs &a, hipStream_t s);

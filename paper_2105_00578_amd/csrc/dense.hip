@@ -270,20 +270,14 @@ static_assert(kMaxW < 64, "Rayleigh-Ritz pivot search: one candidate per lane of
 // by blocks, in place.  One barrier per round.  Before each sweep every pair
 // is tested once: the sweeps stop when no pair would rotate.
 __device__ __forceinline__ void jacobi_pair(int r, int t, int kk, int &p, int &q) {
-  if (t == 0) {
-    p = kk - 1;
-    q = r;
-  } else {
-    p = r + t;
-    if (p >= kk - 1) p -= kk - 1;
-    q = r - t;
-    if (q < 0) q += kk - 1;
-  }
-  if (p > q) {
-    const int tmp = p;
-    p = q;
-    q = tmp;
-  }
+  // written with selects (t varies across lanes)
+  int a = r + t, b = r - t;
+  a = a >= kk - 1 ? a - (kk - 1) : a;
+  b = b < 0 ? b + (kk - 1) : b;
+  a = t == 0 ? kk - 1 : a;
+  b = t == 0 ? r : b;
+  p = min(a, b);
+  q = max(a, b);
 }
 
 // rotations stop once an off-diagonal entry is at rounding level (a few ulps
@@ -291,7 +285,7 @@ __device__ __forceinline__ void jacobi_pair(int r, int t, int kk, int &p, int &q
 // |a_pq| > 2e-16 sqrt(|a_pp a_qq|), compared in squares
 __device__ __forceinline__ bool jacobi_rotates(double apq, double app, double aqq,
                                                double abs_floor) {
-  return fabs(apq) > abs_floor && apq * apq > 4e-32 * fabs(app * aqq);
+  return (fabs(apq) > abs_floor) & (apq * apq > 4e-32 * fabs(app * aqq));
 }
 
 // 1/x and 1/sqrt(x) from the hardware estimates and two Newton steps each
@@ -334,7 +328,11 @@ constexpr int kJacobiThreads = 256;
 // blocks per thread and round: 2 (kMaxW / 2)^2 over kJacobiThreads threads
 constexpr int kJacobiItems = (2 * (kMaxW / 2) * (kMaxW / 2) + kJacobiThreads - 1) / kJacobiThreads;
 
-__device__ double *jacobi_eig(double *A, double *B, double *V, int k, int *flags) {
+// The matrices are at offsets ao (A), bo (B) and vo (V) of the LDS array S;
+// returns the offset of the rotated matrix.
+__device__ __forceinline__ int jacobi_eig(double *S, int ao, int bo, int vo, int k, int *flags) {
+  double *A = S + ao;
+  double *V = S + vo;
   __shared__ double anorm;
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -355,7 +353,7 @@ __device__ double *jacobi_eig(double *A, double *B, double *V, int k, int *flags
   }
   if (t < 3) flags[t] = 0;
   __syncthreads();
-  if (k < 2) return A;
+  if (k < 2) return ao;
   const double abs_floor = 4e-16 * anorm + 1e-300;
   const int npair = kk / 2;              // <= kMaxW / 2 < 64: one pair per lane
   const int nblk = npair * npair;
@@ -373,7 +371,7 @@ __device__ double *jacobi_eig(double *A, double *B, double *V, int k, int *flags
     bI[u] = b / npair;
     bJ[u] = b - bI[u] * npair;
   }
-  double *cur = A, *nxt = B;
+  int cur = ao, nxt = bo;
   for (int sweep = 0; sweep < 40; ++sweep) {
     // flags cycle through three words: the one tested now was cleared two
     // sweeps ago, and read by every thread before the barriers of the last
@@ -386,7 +384,8 @@ __device__ double *jacobi_eig(double *A, double *B, double *V, int k, int *flags
       while (q * (q - 1) / 2 > e) --q;
       while ((q + 1) * q / 2 <= e) ++q;
       const int p = e - q * (q - 1) / 2;
-      if (jacobi_rotates(cur[p * LDA + q], cur[p * LDA + p], cur[q * LDA + q], abs_floor))
+      if (jacobi_rotates(S[cur + p * LDA + q], S[cur + p * LDA + p], S[cur + q * LDA + q],
+                         abs_floor))
         *rot = 1;
     }
     __syncthreads();
@@ -396,9 +395,9 @@ __device__ double *jacobi_eig(double *A, double *B, double *V, int k, int *flags
       {
         int p, q;
         jacobi_pair(r, lane < npair ? lane : 0, kk, p, q);
-        const double apq = cur[p * LDA + q];
-        const double app = cur[p * LDA + p], aqq = cur[q * LDA + q];
-        const bool rr = lane < npair && q < k && jacobi_rotates(apq, app, aqq, abs_floor);
+        const double apq = S[cur + p * LDA + q];
+        const double app = S[cur + p * LDA + p], aqq = S[cur + q * LDA + q];
+        const bool rr = (lane < npair) & (q < k) & jacobi_rotates(apq, app, aqq, abs_floor);
         jacobi_rotation(app, aqq, apq, rr, c, s);
       }
 #pragma unroll
@@ -413,10 +412,9 @@ __device__ double *jacobi_eig(double *A, double *B, double *V, int k, int *flags
         int p0, q0, p1, q1;
         jacobi_pair(r, I, kk, p0, q0);
         jacobi_pair(r, J, kk, p1, q1);
-        const double *M = isv ? V : cur;
-        double *O = isv ? V : nxt;
-        double a00 = M[p0 * LDA + p1], a01 = M[p0 * LDA + q1];
-        double a10 = M[q0 * LDA + p1], a11 = M[q0 * LDA + q1];
+        const int mi = isv ? vo : cur, oi = isv ? vo : nxt;
+        double a00 = S[mi + p0 * LDA + p1], a01 = S[mi + p0 * LDA + q1];
+        double a10 = S[mi + q0 * LDA + p1], a11 = S[mi + q0 * LDA + q1];
         {
           const double b00 = cI * a00 - sI * a10, b10 = sI * a00 + cI * a10;
           const double b01 = cI * a01 - sI * a11, b11 = sI * a01 + cI * a11;
@@ -427,13 +425,13 @@ __device__ double *jacobi_eig(double *A, double *B, double *V, int k, int *flags
           const double b10 = cJ * a10 - sJ * a11, b11 = sJ * a10 + cJ * a11;
           a00 = b00; a01 = b01; a10 = b10; a11 = b11;
         }
-        O[p0 * LDA + p1] = a00;
-        O[p0 * LDA + q1] = a01;
-        O[q0 * LDA + p1] = a10;
-        O[q0 * LDA + q1] = a11;
+        S[oi + p0 * LDA + p1] = a00;
+        S[oi + p0 * LDA + q1] = a01;
+        S[oi + q0 * LDA + p1] = a10;
+        S[oi + q0 * LDA + q1] = a11;
       }
       __syncthreads();
-      double *tmp = cur;
+      const int tmp = cur;
       cur = nxt;
       nxt = tmp;
     }
@@ -457,11 +455,54 @@ __device__ double *jacobi_eig(double *A, double *B, double *V, int k, int *flags
 // Jacobi; the m smallest Ritz pairs give Y = D P W^T Z.  If fewer than m
 // columns survive, the P block is dropped and the step retried once.
 constexpr int kRRThreads = kJacobiThreads;
+
+// (v, i) or (ov, oi), whichever comes first in the order: larger value,
+// then lower index; an index < 0 marks no candidate
+__device__ __forceinline__ void take_better(double &v, int &i, double ov, int oi) {
+  // non-short-circuit operators: selects, no branches
+  const bool b = (oi >= 0) & ((i < 0) | (ov > v) | ((ov == v) & (oi < i)));
+  v = b ? ov : v;
+  i = b ? oi : i;
+}
+
+// Value and index of lane (lane ^ pattern) within rows of 16 lanes (DPP).
+template <int kCtrl>
+__device__ __forceinline__ void dpp_take(double &v, int &i) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, 0xF, 0xF, false);
+  const int oi = __builtin_amdgcn_update_dpp(-1, i, kCtrl, 0xF, 0xF, false);
+  take_better(v, i, __hiloint2double(hi, lo), oi);
+}
+
+// The first (value, index) of the wave in the order above, in every lane
+// (all 64 lanes active): within each row of 16 lanes by DPP moves (swap of
+// neighbours, of pairs, then the half-row and row mirrors, each pairing
+// every lane with one holding the other half's best so far), then across the
+// four rows by lane reads.
+__device__ __forceinline__ void wave_argmax(double &v, int &i) {
+  dpp_take<0xB1>(v, i);    // quad_perm(1, 0, 3, 2)
+  dpp_take<0x4E>(v, i);    // quad_perm(2, 3, 0, 1)
+  dpp_take<0x141>(v, i);   // row_half_mirror
+  dpp_take<0x140>(v, i);   // row_mirror
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  double bv = __hiloint2double(__builtin_amdgcn_readlane(hi, 0), __builtin_amdgcn_readlane(lo, 0));
+  int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r)
+    take_better(bv, bi,
+                __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * r),
+                                 __builtin_amdgcn_readlane(lo, 16 * r)),
+                __builtin_amdgcn_readlane(i, 16 * r));
+  v = bv;
+  i = bi;
+}
 constexpr int kRRItems = (kMaxW * kMaxW + kRRThreads - 1) / kRRThreads;
 
 __global__ __launch_bounds__(kRRThreads) void k_rr(const double *__restrict__ gram, RRArgs a,
                                                    double *Y, double *theta, DevStatus *st) {
-  __shared__ double M1[kMaxW * LDA], M2[kMaxW * LDA], M3[kMaxW * LDA], Wi[kMaxW * LDA];
+  constexpr int MS = kMaxW * LDA;
+  __shared__ double Msh[4 * MS];
+  double *M1 = Msh, *M2 = Msh + MS, *M3 = Msh + 2 * MS, *Wi = Msh + 3 * MS;
   __shared__ double sc[kMaxW], lam[kMaxW], dg[2][kMaxW];
   __shared__ int piv[kMaxW], ipiv[kMaxW], perm[kMaxW];
   __shared__ int flags[3];
@@ -518,14 +559,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rr(const double *__restrict__ gr
       // ties (one candidate per lane: wl <= kMaxW < 64)
       double bv = lane < wl ? dg[k & 1][lane] : 0.0;
       int best = bv > 0.0 ? lane : -1;
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ov = __shfl_xor(bv, off);
-        const int ob = __shfl_xor(best, off);
-        if (ob >= 0 && (best < 0 || ov > bv || (ov == bv && ob < best))) {
-          bv = ov;
-          best = ob;
-        }
-      }
+      wave_argmax(bv, best);
       const int p = (best >= 0 && bv > a.drop_tol) ? best : -1;
       if (p < 0) break;
       const double pval = bv;
@@ -609,8 +643,8 @@ __global__ __launch_bounds__(kRRThreads) void k_rr(const double *__restrict__ gr
       }
       __syncthreads();
       // eigenpairs of A': values on the diagonal, vectors in M2
-      const double *Af = jacobi_eig(M3, M1, M2, k, flags);
-      if (t < k) lam[t] = Af[t * LDA + t];
+      const int af = jacobi_eig(Msh, 2 * MS, 0, MS, k, flags);
+      if (t < k) lam[t] = Msh[af + t * LDA + t];
       __syncthreads();
       if (t < k) {
         int rank = 0;
@@ -661,7 +695,9 @@ __global__ __launch_bounds__(kRRThreads) void k_rr(const double *__restrict__ gr
 // (lowest index on ties).  status: 0, or 1 if H_k is not positive definite.
 __global__ __launch_bounds__(kJacobiThreads) void k_harmonic_ritz(const double *__restrict__ Hg, int k1,
                                                        double *theta, int *status) {
-  __shared__ double Mk[kMaxW * LDA], Mc[kMaxW * LDA], Mv[kMaxW * LDA];
+  constexpr int MS = kMaxW * LDA;
+  __shared__ double Msh[3 * MS];
+  double *Mk = Msh, *Mc = Msh + MS, *Mv = Msh + 2 * MS;
   __shared__ double lam[kMaxW];
   __shared__ int flags[3], bad;
   const int t = threadIdx.x;
@@ -723,8 +759,8 @@ __global__ __launch_bounds__(kJacobiThreads) void k_harmonic_ritz(const double *
   }
   __syncthreads();
   // Mk (the factor) is free now: the second buffer of the rotations
-  const double *Af = jacobi_eig(Mc, Mk, Mv, k1, flags);
-  if (t < k1) lam[t] = Af[t * LDA + t];
+  const int af = jacobi_eig(Msh, MS, 0, 2 * MS, k1, flags);
+  if (t < k1) lam[t] = Msh[af + t * LDA + t];
   __syncthreads();
   if (t == 0) {
     bool used[kMaxW];

@@ -85,12 +85,19 @@ struct GramSrc {
 
 constexpr int kPre = (kCh * kMaxNev + 255) / 256;   // staged values per thread and source
 
-template <typename T, int NT>
+// Tiles: NT x NT tiles of 16 columns cover the padded width W = 16 NT; the
+// upper ones (NT (NT + 1) / 2 per matrix) are formed.  kCompact (NT = 2,
+// w <= 24): two tiles per matrix instead -- T1 = columns 0..15 against
+// 0..15, and T2 = columns w-16..w-1 (rows) against 16..w-1 followed by
+// 0..w-17 (columns), whose entries give the pairs with a column >= 16 (the
+// ones against 0..w-17 by symmetry, stored transposed); one tile per wave.
+template <typename T, int NT, bool kCompact = false>
 __global__ __launch_bounds__(256) void k_gram(GramDev a, GramSrc<T> src,
                                               int64_t rows_per_block, double *partials) {
+  static_assert(!kCompact || NT == 2, "compact tiles are for two-tile widths");
   constexpr int W = 16 * NT;
   constexpr int WP = W + 1;
-  constexpr int NTILES = NT * (NT + 1);   // upper tiles of both matrices
+  constexpr int NTILES = kCompact ? 4 : NT * (NT + 1);   // tiles of both matrices
   constexpr int TPW = (NTILES + 3) / 4;
   __shared__ double sS[kCh * WP];
   __shared__ double sL[kCh * WP];
@@ -104,8 +111,11 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, GramSrc<T> src,
     sS[e] = 0.0;
     sL[e] = 0.0;
   }
-  // tile ownership
-  int tmat[TPW], tti[TPW], ttj[TPW];
+  // tile ownership, and the S columns of this lane's tile row / column
+  const int i16 = lane & 15;
+  const int k4 = lane >> 4;
+  const int wc = a.w - 16;      // compact: T2 row offset, and the width of its two column runs
+  int tmat[TPW], tti[TPW], ttj[TPW], tci[TPW], tcj[TPW];
   d4 acc[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
@@ -113,13 +123,27 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, GramSrc<T> src,
     tmat[q] = -1;
     tti[q] = ttj[q] = 0;
     if (tt < NTILES) {
-      int mat = tt / (NT * (NT + 1) / 2);
-      int r = tt % (NT * (NT + 1) / 2);
-      int ti = 0;
-      while (r >= NT - ti) { r -= NT - ti; ++ti; }
-      tmat[q] = mat;
-      tti[q] = ti;
-      ttj[q] = ti + r;
+      if (kCompact) {
+        tmat[q] = tt >> 1;
+        tti[q] = tt & 1;          // 0: T1, 1: T2
+      } else {
+        int mat = tt / (NT * (NT + 1) / 2);
+        int r = tt % (NT * (NT + 1) / 2);
+        int ti = 0;
+        while (r >= NT - ti) { r -= NT - ti; ++ti; }
+        tmat[q] = mat;
+        tti[q] = ti;
+        ttj[q] = ti + r;
+      }
+    }
+    if (kCompact) {
+      const bool t2 = tti[q] == 1;
+      tci[q] = t2 ? wc + i16 : i16;
+      // T2 columns: 16..w-1, then 0..w-17, then a zero padding column
+      tcj[q] = !t2 ? i16 : (i16 < wc ? 16 + i16 : (i16 < 2 * wc ? i16 - wc : W - 1));
+    } else {
+      tci[q] = tti[q] * 16 + i16;
+      tcj[q] = ttj[q] * 16 + i16;
     }
     acc[q] = d4{0.0, 0.0, 0.0, 0.0};
   }
@@ -152,8 +176,6 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, GramSrc<T> src,
       }
     }
   };
-  const int i16 = lane & 15;
-  const int k4 = lane >> 4;
   __syncthreads();
   if (rb < re) fetch(rb);
   for (int64_t r0 = rb; r0 < re; r0 += kCh) {
@@ -178,8 +200,8 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, GramSrc<T> src,
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
       if (tmat[q] < 0) continue;
-      const int ci = tti[q] * 16 + i16;
-      const int cj = ttj[q] * 16 + i16;
+      const int ci = tci[q];
+      const int cj = tcj[q];
       if (tmat[q] == 0) {
 #pragma unroll 4
         for (int kk = 0; kk < kCh; kk += 4) {
@@ -208,9 +230,20 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, GramSrc<T> src,
     if (tmat[q] < 0) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int gi = tti[q] * 16 + 4 * r + k4;
-      int gj = ttj[q] * 16 + i16;
-      out[(int64_t)tmat[q] * W * W + gi * W + gj] = acc[q][r];
+      if (kCompact && tti[q] == 1) {
+        // T2 entry (row R, column C): the upper entry (R, C) for C >= 16,
+        // R <= C; the upper entry (C, R) for C < w-16, R >= 16 (pairs with
+        // both below 16 come from T1); nothing for the padding column
+        const int R = wc + 4 * r + k4, C = tcj[q];
+        int gi = -1, gj = -1;
+        if (C >= 16 && C < a.w && R <= C) { gi = R; gj = C; }
+        if (C < wc && R >= 16) { gi = C; gj = R; }
+        if (gi >= 0) out[(int64_t)tmat[q] * W * W + gi * W + gj] = acc[q][r];
+      } else {
+        int gi = (kCompact ? 0 : tti[q] * 16) + 4 * r + k4;
+        int gj = (kCompact ? 0 : ttj[q] * 16) + i16;
+        out[(int64_t)tmat[q] * W * W + gi * W + gj] = acc[q][r];
+      }
     }
   }
 }
@@ -219,7 +252,7 @@ __global__ __launch_bounds__(256) void k_gram(GramDev a, GramSrc<T> src,
 // entries, 16 thread groups sum interleaved subsets of the partial blocks,
 // and the 16 subset sums are added in a fixed order.
 __global__ __launch_bounds__(256) void k_gram_reduce(const double *partials, int nblocks,
-                                                     int NT, double *out) {
+                                                     int NT, int w, double *out) {
   const int W = 16 * NT;
   const int E = 2 * W * W;
   const int t = threadIdx.x;
@@ -230,7 +263,7 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double *partials, int
   if (e < E) {
     int ij = e % (W * W);
     int i = ij / W, j = ij - i * W;
-    if (i / 16 <= j / 16) {
+    if (i <= j && j < w) {
       int b = sub;
       for (; b + 16 < nblocks; b += 32) {
         s0 += partials[(int64_t)b * E + e];
@@ -1140,8 +1173,12 @@ int gram(const T *X, const T *LX, const T *H, const T *LH, const T *P, const T *
                          partials);
       break;
     case 2:
-      hipLaunchKernelGGL((k_gram<T, 2>), dim3(nb), dim3(256), 0, s, d, sp, rows_per_block,
-                         partials);
+      if (d.w <= 24)
+        hipLaunchKernelGGL((k_gram<T, 2, true>), dim3(nb), dim3(256), 0, s, d, sp,
+                           rows_per_block, partials);
+      else
+        hipLaunchKernelGGL((k_gram<T, 2>), dim3(nb), dim3(256), 0, s, d, sp, rows_per_block,
+                           partials);
       break;
     case 3:
       hipLaunchKernelGGL((k_gram<T, 3>), dim3(nb), dim3(256), 0, s, d, sp, rows_per_block,
@@ -1152,7 +1189,7 @@ int gram(const T *X, const T *LX, const T *H, const T *LH, const T *P, const T *
   }
   int W = 16 * NT;
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ceil_div(2 * W * W, 16)), dim3(256), 0, s,
-                     (const double *)partials, nb, NT, gram_out);
+                     (const double *)partials, nb, NT, d.w, gram_out);
   return hipGetLastError() == hipSuccess ? SPHX_OK : SPHX_E_HIP;
 }
 

@@ -324,7 +324,8 @@ def run(args):
         mss = sum(s.phases_ms["spmm"] for s in sts)
         r = dict(
             ms_per_step=dt, time_to_eigvecs_ms=float(np.median(eig_ms)),
-            iterations=st.iterations, rho_max=max(st.rho[:d]), cut=cut, imbalance=imb,
+            iterations=st.iterations, promoted=int(st.promoted), rho_max=max(st.rho[:d]),
+            cut=cut, imbalance=imb,
             cheb_gbs=gbp / (msp * 1e-3) if msp > 0 else 0.0,
             cheb_avg_us=msp / max(1, sum(s.precond_calls for s in sts)) * 1e3,
             cheb_calls=sum(s.precond_calls for s in sts),
@@ -385,6 +386,7 @@ def run(args):
         "ms_per_step_fp64": round(f64["ms_per_step"], 3),
         "spmm_gbs_fp64": round(f64["cheb_gbs"] if cheb else f64["spmm_gbs"], 2),
         "iterations": {"mixed": mx["iterations"], "fp64": f64["iterations"]},
+        "promoted": mx["promoted"],
         "rho_max": {"mixed": mx["rho_max"], "fp64": f64["rho_max"]},
         "cut": {"mixed": mx["cut"], "fp64": f64["cut"]},
         "imbalance": {"mixed": mx["imbalance"], "fp64": f64["imbalance"]},

@@ -516,10 +516,9 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
   const double *bdiag = gen ? w.d64 : nullptr;
   const double *dinv = nullptr;
   ChebCoef ck;
-  if (o.precond == SPHX_PRECOND_CHEBYSHEV) {
-    double hi = gen ? 2.0 : 2.0 * ds.max_wdeg;
-    ck = cheb_coef(o.cheb_degree, hi / o.cheb_ratio, hi);
-  }
+  // Gershgorin bound of the operator (B^-1 L for the generalized pencil)
+  const double l_norm = gen ? 2.0 : 2.0 * ds.max_wdeg;
+  if (o.precond == SPHX_PRECOND_CHEBYSHEV) ck = cheb_coef(o.cheb_degree, l_norm / o.cheb_ratio, l_norm);
   if ((o.precond == SPHX_PRECOND_CHEBYSHEV || o.precond == SPHX_PRECOND_GMRES) && gen) {
     hipLaunchKernelGGL(k_inverse, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, w.d64, w.dinv,
                        n);
@@ -654,12 +653,19 @@ int solve(sphx_handle *h, sphx_graph *g, int m, const sphx_options &o, const voi
     pl.end(tid, s);
     UpdateArgs ub{n, m, ld, act, 1, have_p ? 1 : 0};
     tid = pl.begin(PH_UPDATE, 0.0, s);
-    // FP64 carries L P along as L H y + L P z.  FP32 forms it by a product:
-    // the combination keeps the absolute rounding of the stored FP32 products
-    // of earlier steps while P shrinks, and once P is rescaled in the
-    // Rayleigh-Ritz step that error dominates its projected entries (converged
-    // columns then diverged near the tolerance)
-    constexpr bool lp_product = std::is_same_v<T, float>;
+    // L P is carried along as L H y + L P z, except in FP32 near its rounding
+    // floor, where it is formed by a product: the combination keeps the
+    // absolute rounding of the stored FP32 products of earlier steps while P
+    // shrinks, and once P is rescaled in the Rayleigh-Ritz step that error
+    // dominates its projected entries (converged columns then diverged near
+    // the tolerance).  Near the floor: 2^-24 ||L|| / theta_1 (the relative
+    // residual of a rounded eigenvector at most, theta_1 the smallest
+    // non-trivial Ritz value) above a tenth of the tolerance.
+    bool lp_product = false;
+    if constexpr (std::is_same_v<T, float>) {
+      const double th1 = hs->theta[m > 1 ? 1 : 0];
+      lp_product = !(th1 > 0.0) || 0x1p-24 * l_norm / th1 > 0.1 * o.tol;
+    }
     SPHX_TRY(launch_update<T>(w.X, H, w.P, w.LH, lp_product ? nullptr : w.LP, w.Y, ub, s));
     pl.end(tid, s);
     if (lp_product) {

@@ -119,9 +119,9 @@ __global__ __launch_bounds__(256) void k_gain_block(const int32_t *__restrict__ 
                                                     int32_t *tgt, S *gain) {
   __shared__ int32_t sp[kRefineMaxDeg];
   __shared__ int32_t cnt[kLdsParts];
-  // per-thread candidates and own-part sums, combined by thread 0 in thread
-  // order (the combination is exact and order-free: a maximum under a total
-  // order and an integer sum)
+  // per-thread candidates and own-part sums, combined by a tree in LDS (the
+  // combination is exact and order-free: a maximum under a total order and
+  // an integer sum)
   __shared__ S rc[256], ra[256];
   __shared__ int rt[256];
   constexpr bool kUnit = std::is_same_v<WT, Unit>;
@@ -183,16 +183,23 @@ __global__ __launch_bounds__(256) void k_gain_block(const int32_t *__restrict__ 
     __syncthreads();
     if (table)   // clear the counts of this row (every read above is done)
       for (int j = tid; j < d; j += 256) cnt[sp[j]] = 0;
-    if (tid == 0) {
-      S B = rc[0], A = ra[0];
-      int T = rt[0];
-      for (int q = 1; q < 256; ++q) {
-        A += ra[q];
-        if (better(rc[q], rt[q], B, T)) {
-          B = rc[q];
-          T = rt[q];
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) {
+        S B = rc[tid];
+        int T = rt[tid];
+        if (better(rc[tid + h], rt[tid + h], B, T)) {
+          B = rc[tid + h];
+          T = rt[tid + h];
         }
+        rc[tid] = B;
+        rt[tid] = T;
+        ra[tid] += ra[tid + h];
       }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const S B = rc[0], A = ra[0];
+      const int T = rt[0];
       const bool cand = T >= 0 && B - A > 0;
       tgt[v] = cand ? T : -1;
       gain[v] = cand ? B - A : (S)0;
@@ -259,8 +266,9 @@ __global__ __launch_bounds__(256) void k_movers_wave(const int32_t *__restrict__
                                                      const int32_t *__restrict__ part,
                                                      const int32_t *__restrict__ tgt,
                                                      const S *__restrict__ gain, uint8_t *mv) {
-  // lane sums through LDS, added by lane 0 in lane order; the row loop is
-  // uniform over the block (rows r0 + wave) so every wave reaches the barriers
+  // lane sums through LDS, added by a tree per wave (exact integer sums: the
+  // order does not matter); the row loop is uniform over the block (rows
+  // r0 + wave) so every wave reaches the barriers
   __shared__ S lanes[256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nr = *nrows;
@@ -280,11 +288,11 @@ __global__ __launch_bounds__(256) void k_movers_wave(const int32_t *__restrict__
     }
     lanes[threadIdx.x] = g2;
     __syncthreads();
-    if (lane == 0 && v >= 0) {
-      S tot = 0;
-      for (int q = 0; q < 64; ++q) tot += lanes[wave * 64 + q];
-      mv[v] = (t >= 0 && tot > 0) ? 1 : 0;
+    for (int h = 32; h > 0; h >>= 1) {
+      if (lane < h) lanes[threadIdx.x] += lanes[threadIdx.x + h];
+      __syncthreads();
     }
+    if (lane == 0 && v >= 0) mv[v] = (t >= 0 && lanes[threadIdx.x] > 0) ? 1 : 0;
     __syncthreads();
   }
 }

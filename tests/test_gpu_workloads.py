@@ -81,6 +81,31 @@ def test_grid128_chebyshev_k64(handle, prec):
     assert imb == 1.0
 
 
+@pytest.mark.parametrize("seed", [3, 7, 12345])
+def test_grid128_mixed_stays_in_fp32(handle, seed):
+    """The FP32 iteration must not drift near its rounding floor: with L P
+    carried as a combination of stored FP32 products, seeds 3 and 12345 of
+    this solve diverge after reaching rho ~ 1e-3 and go to FP64 (159 and 171
+    iterations; the other seeds of 1..12 take 29..42 either way)."""
+    g = _grid128()
+    opts = sx.options_default(True, sx.PRECOND_CHEBYSHEV, precision=sx.MIXED, seed=seed)
+    rp, col, w = upload(g)
+    G = sx.Graph(handle, rp, col, w)
+    lam, V, st = sx.eigensolve(handle, G, 7, opts)
+    assert st.promoted == 0
+    assert st.iterations < 60
+    assert max(st.rho[:7]) <= 1e-3
+
+
+_GRID = {}
+
+
+def _grid128():
+    if "g" not in _GRID:
+        _GRID["g"] = graphgen.config_graph("grid7_128")
+    return _GRID["g"]
+
+
 @pytest.mark.parametrize("prec", [sx.MIXED, sx.FP64])
 def test_rmat22_generalized_jacobi_k16(handle, prec):
     """R-MAT scale 22 (LCC), generalized problem, Jacobi, K = 16, tol 1e-2."""
